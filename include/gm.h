@@ -1,0 +1,224 @@
+/*
+ * gm.h -- C ABI of the MI355X Gumbel-Max sketch library (libgm.so).
+ *
+ * The library computes k-register Gumbel-Max sketches of sparse non-negative
+ * vectors ("Fast Gumbel-Max Sketch and its Applications", Zhang, Qi, Wang et
+ * al., arXiv:2302.05176) and the two estimators built on them.
+ *
+ *   s_j(v) = argmin_{i in N+(v)} E_ij / v_i,   y_j(v) = min_{i in N+(v)} E_ij / v_i,
+ *
+ * j = 0..k-1, with E_ij ~ Exp(1) consistent across vectors (Sec. 1, Eq. (1)
+ * and Eq. (2); N+(v) is the set of indices with v_i > 0).  s is the
+ * Gumbel-ArgMax sketch (probability-Jaccard estimation), y the Lemiesz sketch
+ * (weighted cardinality estimation); x_j = -ln y_j is the Gumbel-Max variable.
+ *
+ * Two forms with identical distributions but different concrete draws:
+ *   FastGM form  -- element i's k variables are generated as ascending order
+ *                   statistics (Eq. (7)-(8)) routed to registers by a
+ *                   Fisher-Yates permutation (Sec. 2.2); an element stops at
+ *                   its first arrival later than the largest register
+ *                   (FastPrune), giving O(k ln k + n+) work (Sec. 2.5).
+ *   plain form   -- E_ij drawn independently per (i, j); O(k n+) work
+ *                   (Sec. 1, the straightforward method).
+ * The draws are fixed by the library's draw specification (splitmix64 hash
+ * of (seed, i, step), uniform (x>>11 + 1/2) 2^-53, a fixed-order -ln), so a
+ * sketch is a pure function of (multiset of (index, weight) entries, k, seed,
+ * form): it does not depend on entry order, batch composition, stream or
+ * launch configuration.  Sketches are comparable only when built with the
+ * same (k, seed, form).
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers on the current HIP device,
+ *     owned by the caller, and must stay valid until `stream` reaches the
+ *     call.  Every call is asynchronous on `stream` (0 = null stream), except
+ *     gm_get_data_errors, which synchronises `stream`.
+ *   - Input vectors are CSR rows: vector v holds entries
+ *     [offsets[v], offsets[v+1]) of `indices` (int32, must be >= 0) and
+ *     `weights` (fp32).  offsets has nvec+1 int64 entries and offsets[0] is
+ *     the base (need not be 0).  Duplicate indices are allowed (a stream
+ *     element seen twice changes nothing when its weight repeats).
+ *   - Outputs are row-major: register j of vector v is out_idx[v*k + j]
+ *     (int32 index s_j) and out_val[v*k + j] (fp64 key y_j).
+ *   - Weight 0 means "not in N+" and the entry is skipped.  A vector with no
+ *     positive weight gets empty registers (index -1, value +inf).
+ *   - Argument errors (null pointer with nvec > 0, nvec < 0, k outside
+ *     [1, GM_K_MAX]) are detected on the host; the call returns
+ *     GM_ERR_INVALID_ARG and enqueues nothing.
+ *   - Data errors (a negative, NaN or infinite weight, a negative index, or
+ *     offsets[v+1] < offsets[v]) are detected on the device: the vector's
+ *     registers become (index -2, value NaN) and a sticky per-device counter
+ *     is incremented once per bad vector (read it with gm_get_data_errors).
+ *   - The library keeps a small workspace per device and per stream (an error
+ *     counter, and for the FastGM form a planner list of nvec int32), created
+ *     or grown by the first call that needs it -- make that call outside any
+ *     stream capture -- and released by gm_release().
+ */
+#ifndef GM_H
+#define GM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GM_OK = 0,
+    GM_ERR_INVALID_ARG = 1,
+    GM_ERR_OUT_OF_MEMORY = 2,
+    GM_ERR_DEVICE = 3,
+    GM_ERR_UNSUPPORTED = 4
+} gm_status;
+
+typedef enum { GM_FORM_FASTGM = 0, GM_FORM_PLAIN = 1 } gm_form;
+
+/* Largest register count supported by the kernels. */
+#define GM_K_MAX 4096
+
+/*
+ * gm_sketch -- FastGM form (Algorithm 1 / Algorithm 2 semantics: ascending
+ * arrivals per element, Fisher-Yates routing, FastPrune against the running
+ * maximum register), for nvec CSR vectors with the same k.
+ *   indices  [nnz] int32   element indices (>= 0)
+ *   weights  [nnz] fp32    element weights (>= 0, finite)
+ *   offsets  [nvec+1] int64
+ *   nvec     number of vectors (0 is allowed: nothing is launched)
+ *   k        registers per sketch, 1..GM_K_MAX
+ *   seed     sketch seed (the hash key of every draw)
+ *   out_idx  [nvec*k] int32  s_j
+ *   out_val  [nvec*k] fp64   y_j
+ */
+gm_status gm_sketch(const int32_t *indices, const float *weights, const int64_t *offsets,
+                    int64_t nvec, int32_t k, uint64_t seed,
+                    int32_t *out_idx, double *out_val, hipStream_t stream);
+
+/*
+ * gm_sketch_plain -- plain form of Eq. (1)/(2): every (entry, register) key
+ * is drawn and the minimum kept; O(k n+) per vector.  Same arguments and
+ * layout as gm_sketch.  Register j of a k-register plain sketch equals
+ * register j of any larger plain sketch with the same seed.
+ */
+gm_status gm_sketch_plain(const int32_t *indices, const float *weights, const int64_t *offsets,
+                          int64_t nvec, int32_t k, uint64_t seed,
+                          int32_t *out_idx, double *out_val, hipStream_t stream);
+
+/*
+ * gm_sketch_batched -- vectors with individual register counts, in one call.
+ *   k_per_vec    [nvec] int32 (device)  k of vector v, 1..k_max
+ *   out_offsets  [nvec+1] int64 (device) registers of vector v are written to
+ *                out_*[out_offsets[v] .. out_offsets[v] + k_per_vec[v])
+ *   k_max        host-side upper bound of k_per_vec (1..GM_K_MAX)
+ *   form         GM_FORM_FASTGM or GM_FORM_PLAIN
+ * A vector whose k_per_vec is outside [1, k_max] is a data error (its first
+ * out_offsets[v+1]-out_offsets[v] registers are poisoned).
+ */
+gm_status gm_sketch_batched(const int32_t *indices, const float *weights, const int64_t *offsets,
+                            int64_t nvec, const int32_t *k_per_vec, const int64_t *out_offsets,
+                            int32_t k_max, uint64_t seed, gm_form form,
+                            int32_t *out_idx, double *out_val, hipStream_t stream);
+
+/*
+ * gm_jaccard_est -- probability-Jaccard estimate of Sec. 1:
+ *   out[p] = #{ j : a[p*k+j] == b[p*k+j] and a[p*k+j] >= 0 } / k
+ * for npairs row-major pairs of Gumbel-ArgMax sketches (Theorem 1: unbiased
+ * for J_P with variance J_P (1 - J_P) / k).  Empty (-1) and poisoned (-2)
+ * registers never match.
+ */
+gm_status gm_jaccard_est(const int32_t *idx_a, const int32_t *idx_b, int64_t npairs, int32_t k,
+                         double *out, hipStream_t stream);
+
+/*
+ * gm_jaccard_est_pairs -- same estimate for pairs of rows of a device-resident
+ * sketch store: out[p] = J_hat(store[ia[p]], store[ib[p]]), rows of k int32.
+ *   store_idx [nstore*k] int32, ia/ib [npairs] int64 row numbers (device).
+ * Row numbers outside [0, nstore) give out[p] = NaN and count as data errors.
+ */
+gm_status gm_jaccard_est_pairs(const int32_t *store_idx, int64_t nstore, int32_t k,
+                               const int64_t *ia, const int64_t *ib, int64_t npairs,
+                               double *out, hipStream_t stream);
+
+/*
+ * gm_wcard_est -- weighted-cardinality estimate of Sec. 1 (Lemiesz):
+ *   out[v] = (k - 1) / (y_0 + y_1 + ... + y_{k-1})
+ * with the sum taken left to right in fp64 (Theorem 2: unbiased).  k >= 2.
+ * An empty sketch (+inf registers) gives 0; a poisoned one gives NaN.
+ */
+gm_status gm_wcard_est(const double *val, int64_t nvec, int32_t k, double *out,
+                       hipStream_t stream);
+
+/*
+ * gm_merge -- sketch of a union from sketches of its parts (Sec. 2.3):
+ * register j of the result is the lexicographic (y, s) minimum over the r
+ * input sketches' register j (r row-major sketches of k registers in
+ * in_idx/in_val, result in out_idx/out_val).  r >= 1.
+ */
+gm_status gm_merge(const int32_t *in_idx, const double *in_val, int64_t r, int32_t k,
+                   int32_t *out_idx, double *out_val, hipStream_t stream);
+
+/*
+ * gm_get_data_errors -- synchronises `stream`, then stores in *host_count the
+ * number of poisoned vectors (and invalid store rows) seen on the current
+ * device since the library was loaded or last reset.
+ */
+gm_status gm_get_data_errors(int64_t *host_count, hipStream_t stream);
+
+/* gm_reset_data_errors -- zero the current device's data-error counter
+ * (asynchronous on `stream`). */
+gm_status gm_reset_data_errors(hipStream_t stream);
+
+/*
+ * gm_set_option -- process-wide tuning and testing knobs (defaults in
+ * brackets).  They change how much work is done or which internal path runs,
+ * never the result:
+ *   GM_OPT_POS_BITS      [24] entry-position bits in a packed FastGM register,
+ *                        8..62; more bits means fewer key bits and more
+ *                        exact re-resolutions of tied prefixes.
+ *   GM_OPT_T0_SCALE_PPM  [1000000] scale of the closed-form pruning threshold
+ *                        in parts per million; small values force the
+ *                        enlarge-and-repeat fallback.
+ *   GM_OPT_MAP_LOAD      [10] displaced permutation positions a lane may
+ *                        track, 0..16; beyond it an element moves to the
+ *                        segment path, where 16 or 64 lanes walk it
+ *                        together (0 sends almost every element there).
+ *   GM_OPT_REPUBLISH     [4] light iterations between republishes of the
+ *                        running maximum register, a power of two.
+ *   GM_OPT_STATS         [0] 1 makes FastGM calls accumulate work counters
+ *                        (read them with gm_get_stats); costs a few atomics
+ *                        per vector.
+ * Returns GM_ERR_INVALID_ARG for an unknown option or out-of-range value.
+ */
+typedef enum {
+    GM_OPT_POS_BITS = 0,
+    GM_OPT_T0_SCALE_PPM = 1,
+    GM_OPT_MAP_LOAD = 2,
+    GM_OPT_REPUBLISH = 3,
+    GM_OPT_STATS = 4
+} gm_option;
+gm_status gm_set_option(gm_option opt, int64_t value);
+
+/*
+ * gm_get_stats -- synchronises `stream`, then copies the first n (<= 16)
+ * FastGM work counters of the current device, summed over calls made while
+ * GM_OPT_STATS was 1: [0] vectors, [1] light-path wave iterations, [2] light
+ * arrivals drawn, [3] of which at or below the pruning threshold, [4]
+ * elements started on the light path, [5] elements moved to the
+ * wave-cooperative path, [6] its 64-arrival batches, [7] extra passes after
+ * an unfilled register, [8] exact index resolutions.
+ * gm_reset_stats -- synchronises `stream` and zeroes the counters.
+ */
+gm_status gm_get_stats(int64_t *host_counters, int32_t n, hipStream_t stream);
+gm_status gm_reset_stats(hipStream_t stream);
+
+/* gm_status_string -- static text for a status code. */
+const char *gm_status_string(gm_status status);
+
+/* gm_release -- free the library's per-device workspaces (call when no
+ * stream still has library work queued). */
+void gm_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GM_H */

@@ -1,0 +1,86 @@
+"""ctypes view of libgm.so (the C ABI in include/gm.h).
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation of any entry point.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from . import build as _build
+
+GM_OK = 0
+GM_ERR_INVALID_ARG = 1
+GM_ERR_OUT_OF_MEMORY = 2
+GM_ERR_DEVICE = 3
+GM_ERR_UNSUPPORTED = 4
+
+GM_FORM_FASTGM = 0
+GM_FORM_PLAIN = 1
+
+GM_K_MAX = 4096
+
+OPTIONS = {"pos_bits": 0, "t0_scale_ppm": 1, "map_load": 2, "republish": 3, "stats": 4}
+STATS = ["vectors", "iterations", "arrivals", "kept", "elements", "heavy", "heavy_batches",
+         "passes", "resolves"]
+
+_lib = None
+
+
+class GMError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} (status {status})")
+
+
+def path() -> str:
+    return _build.LIB
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB):
+        raise ImportError(
+            f"libgm.so not found at {_build.LIB}; build it with "
+            "`python -m paper_2302_05176_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(_build.LIB)
+    p, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                             ctypes.c_uint64, ctypes.c_double)
+    st = ctypes.c_int
+    L.gm_sketch.argtypes = [p, p, p, i64, i32, u64, p, p, p]
+    L.gm_sketch_plain.argtypes = [p, p, p, i64, i32, u64, p, p, p]
+    L.gm_sketch_batched.argtypes = [p, p, p, i64, p, p, i32, u64, ctypes.c_int, p, p, p]
+    L.gm_jaccard_est.argtypes = [p, p, i64, i32, p, p]
+    L.gm_jaccard_est_pairs.argtypes = [p, i64, i32, p, p, i64, p, p]
+    L.gm_wcard_est.argtypes = [p, i64, i32, p, p]
+    L.gm_merge.argtypes = [p, p, i64, i32, p, p, p]
+    L.gm_get_data_errors.argtypes = [ctypes.POINTER(ctypes.c_int64), p]
+    L.gm_reset_data_errors.argtypes = [p]
+    L.gm_set_option.argtypes = [ctypes.c_int, i64]
+    L.gm_status_string.argtypes = [ctypes.c_int]
+    L.gm_status_string.restype = ctypes.c_char_p
+    L.gm_get_stats.argtypes = [ctypes.POINTER(ctypes.c_int64), i32, p]
+    L.gm_reset_stats.argtypes = [p]
+    L.gm_release.argtypes = []
+    L.gm_release.restype = None
+    for name in ("gm_sketch", "gm_sketch_plain", "gm_sketch_batched", "gm_jaccard_est",
+                 "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_get_data_errors",
+                 "gm_reset_data_errors", "gm_set_option", "gm_get_stats", "gm_reset_stats"):
+        getattr(L, name).restype = st
+    _lib = L
+    return L
+
+
+def status_string(status: int) -> str:
+    try:
+        return load().gm_status_string(int(status)).decode()
+    except ImportError:
+        return "unknown"
+
+
+def check(status: int, what: str) -> None:
+    if status != GM_OK:
+        raise GMError(status, what)

@@ -1,0 +1,323 @@
+// gm_api.hip -- the C ABI declared in include/gm.h.
+//
+// Host side only: argument validation (synchronous, nothing is enqueued on
+// error), the per-device workspace (data-error counter), process-wide tuning
+// options, and dispatch to the kernel launchers.  No call allocates on the
+// steady-state path: the workspace is created by the first call on a device.
+#include <map>
+#include <mutex>
+
+#include "gm.h"
+#include "gm_common.h"
+
+namespace gm {
+hipError_t launch_plain(const SketchArgs& p, hipStream_t stream);
+hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
+                         int republish, int32_t* list, void* plan, int cus,
+                         unsigned long long* stats, hipStream_t stream);
+size_t plan_state_bytes();
+hipError_t launch_jaccard(const int32_t* a, const int32_t* b, int64_t npairs, int32_t k,
+                          double* out, hipStream_t stream);
+hipError_t launch_jaccard_pairs(const int32_t* store, int64_t nstore, int32_t k, const int64_t* ia,
+                                const int64_t* ib, int64_t npairs, double* out,
+                                unsigned long long* err, hipStream_t stream);
+hipError_t launch_wcard(const double* val, int64_t nvec, int32_t k, double* out,
+                        hipStream_t stream);
+hipError_t launch_merge(const int32_t* in_idx, const double* in_val, int64_t r, int32_t k,
+                        int32_t* out_idx, double* out_val, hipStream_t stream);
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream);
+}  // namespace gm
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Planner workspace of one (device, stream): the vector list and the class
+// counters.  Keyed by stream so that calls on different streams never share it.
+struct PlanWorkspace {
+  int32_t* list = nullptr;
+  int64_t cap = 0;
+  void* plan = nullptr;
+};
+
+constexpr int kStatSlots = 16;
+
+struct DeviceState {
+  unsigned long long* err = nullptr;
+  unsigned long long* stats = nullptr;  // FastGM counters, when enabled
+  int cus = 0;
+  std::map<hipStream_t, PlanWorkspace> plans;
+};
+
+std::mutex g_mu;
+DeviceState g_dev[kMaxDevices];
+
+// Tuning / testing options (process-wide).
+int g_pos_bits = 24;
+double g_t0_scale = 1.0;
+int g_map_load = 10;
+int g_republish = 4;
+bool g_stats = false;
+
+gm_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return GM_OK;
+  if (e == hipErrorOutOfMemory) return GM_ERR_OUT_OF_MEMORY;
+  return GM_ERR_DEVICE;
+}
+
+// Workspace of the current device (created on first use).
+gm_status device_state(DeviceState** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GM_ERR_DEVICE;
+  if (dev < 0 || dev >= kMaxDevices) return GM_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceState& st = g_dev[dev];
+  if (!st.err) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(unsigned long long));
+    if (e != hipSuccess) return from_hip(e);
+    e = hipMemset(p, 0, sizeof(unsigned long long));
+    if (e != hipSuccess) {
+      (void)hipFree(p);
+      return from_hip(e);
+    }
+    st.err = static_cast<unsigned long long*>(p);
+    void* q = nullptr;
+    e = hipMalloc(&q, sizeof(unsigned long long) * kStatSlots);
+    if (e != hipSuccess) return from_hip(e);
+    e = hipMemset(q, 0, sizeof(unsigned long long) * kStatSlots);
+    if (e != hipSuccess) return from_hip(e);
+    st.stats = static_cast<unsigned long long*>(q);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return from_hip(e);
+    st.cus = prop.multiProcessorCount;
+  }
+  *out = &st;
+  return GM_OK;
+}
+
+// Planner workspace for `stream` with room for nvec vector ids.  Grows (with
+// hipMalloc) only when a call needs more room than any earlier call did.
+gm_status plan_workspace(DeviceState* st, hipStream_t stream, int64_t nvec, PlanWorkspace** out) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  PlanWorkspace& ws = st->plans[stream];
+  if (!ws.plan) {
+    hipError_t e = hipMalloc(&ws.plan, gm::plan_state_bytes());
+    if (e != hipSuccess) return from_hip(e);
+  }
+  if (ws.cap < nvec) {
+    if (ws.list) (void)hipFree(ws.list);
+    ws.list = nullptr;
+    ws.cap = 0;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(int32_t) * static_cast<size_t>(nvec));
+    if (e != hipSuccess) return from_hip(e);
+    ws.list = static_cast<int32_t*>(p);
+    ws.cap = nvec;
+  }
+  *out = &ws;
+  return GM_OK;
+}
+
+gm_status sketch_common(const int32_t* indices, const float* weights, const int64_t* offsets,
+                        int64_t nvec, int32_t k_uniform, const int32_t* kvec,
+                        const int64_t* outoff, int32_t k_max, uint64_t seed, gm_form form,
+                        int32_t* out_idx, double* out_val, hipStream_t stream) {
+  if (nvec < 0 || k_max < 1 || k_max > GM_K_MAX) return GM_ERR_INVALID_ARG;
+  if (form != GM_FORM_FASTGM && form != GM_FORM_PLAIN) return GM_ERR_INVALID_ARG;
+  if (nvec == 0) return GM_OK;
+  if (!indices || !weights || !offsets || !out_idx || !out_val) return GM_ERR_INVALID_ARG;
+  DeviceState* st = nullptr;
+  gm_status s = device_state(&st);
+  if (s != GM_OK) return s;
+  gm::SketchArgs a;
+  a.idx = indices;
+  a.w = weights;
+  a.off = offsets;
+  a.nvec = nvec;
+  a.k_uniform = k_uniform;
+  a.kvec = kvec;
+  a.outoff = outoff;
+  a.k_max = k_max;
+  a.seed_mix = gm::mix(seed);
+  a.out_idx = out_idx;
+  a.out_val = out_val;
+  a.err = st->err;
+  if (form == GM_FORM_PLAIN) return from_hip(gm::launch_plain(a, stream));
+  if (nvec > 0x7FFFFFFF) return GM_ERR_UNSUPPORTED;
+  PlanWorkspace* ws = nullptr;
+  s = plan_workspace(st, stream, nvec, &ws);
+  if (s != GM_OK) return s;
+  return from_hip(gm::launch_fastgm(a, g_pos_bits, g_t0_scale, g_map_load, g_republish, ws->list,
+                                    ws->plan, st->cus, g_stats ? st->stats : nullptr, stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+gm_status gm_sketch(const int32_t* indices, const float* weights, const int64_t* offsets,
+                    int64_t nvec, int32_t k, uint64_t seed, int32_t* out_idx, double* out_val,
+                    hipStream_t stream) {
+  if (k < 1 || k > GM_K_MAX) return GM_ERR_INVALID_ARG;
+  return sketch_common(indices, weights, offsets, nvec, k, nullptr, nullptr, k, seed,
+                       GM_FORM_FASTGM, out_idx, out_val, stream);
+}
+
+gm_status gm_sketch_plain(const int32_t* indices, const float* weights, const int64_t* offsets,
+                          int64_t nvec, int32_t k, uint64_t seed, int32_t* out_idx,
+                          double* out_val, hipStream_t stream) {
+  if (k < 1 || k > GM_K_MAX) return GM_ERR_INVALID_ARG;
+  return sketch_common(indices, weights, offsets, nvec, k, nullptr, nullptr, k, seed,
+                       GM_FORM_PLAIN, out_idx, out_val, stream);
+}
+
+gm_status gm_sketch_batched(const int32_t* indices, const float* weights, const int64_t* offsets,
+                            int64_t nvec, const int32_t* k_per_vec, const int64_t* out_offsets,
+                            int32_t k_max, uint64_t seed, gm_form form, int32_t* out_idx,
+                            double* out_val, hipStream_t stream) {
+  if (nvec > 0 && (!k_per_vec || !out_offsets)) return GM_ERR_INVALID_ARG;
+  return sketch_common(indices, weights, offsets, nvec, k_max, k_per_vec, out_offsets, k_max,
+                       seed, form, out_idx, out_val, stream);
+}
+
+gm_status gm_jaccard_est(const int32_t* idx_a, const int32_t* idx_b, int64_t npairs, int32_t k,
+                         double* out, hipStream_t stream) {
+  if (npairs < 0 || k < 1) return GM_ERR_INVALID_ARG;
+  if (npairs == 0) return GM_OK;
+  if (!idx_a || !idx_b || !out) return GM_ERR_INVALID_ARG;
+  return from_hip(gm::launch_jaccard(idx_a, idx_b, npairs, k, out, stream));
+}
+
+gm_status gm_jaccard_est_pairs(const int32_t* store_idx, int64_t nstore, int32_t k,
+                               const int64_t* ia, const int64_t* ib, int64_t npairs, double* out,
+                               hipStream_t stream) {
+  if (npairs < 0 || nstore < 0 || k < 1) return GM_ERR_INVALID_ARG;
+  if (npairs == 0) return GM_OK;
+  if (!store_idx || !ia || !ib || !out) return GM_ERR_INVALID_ARG;
+  DeviceState* st = nullptr;
+  gm_status s = device_state(&st);
+  if (s != GM_OK) return s;
+  return from_hip(
+      gm::launch_jaccard_pairs(store_idx, nstore, k, ia, ib, npairs, out, st->err, stream));
+}
+
+gm_status gm_wcard_est(const double* val, int64_t nvec, int32_t k, double* out,
+                       hipStream_t stream) {
+  if (nvec < 0 || k < 2) return GM_ERR_INVALID_ARG;
+  if (nvec == 0) return GM_OK;
+  if (!val || !out) return GM_ERR_INVALID_ARG;
+  return from_hip(gm::launch_wcard(val, nvec, k, out, stream));
+}
+
+gm_status gm_merge(const int32_t* in_idx, const double* in_val, int64_t r, int32_t k,
+                   int32_t* out_idx, double* out_val, hipStream_t stream) {
+  if (r < 1 || k < 1) return GM_ERR_INVALID_ARG;
+  if (!in_idx || !in_val || !out_idx || !out_val) return GM_ERR_INVALID_ARG;
+  return from_hip(gm::launch_merge(in_idx, in_val, r, k, out_idx, out_val, stream));
+}
+
+gm_status gm_get_data_errors(int64_t* host_count, hipStream_t stream) {
+  if (!host_count) return GM_ERR_INVALID_ARG;
+  DeviceState* st = nullptr;
+  gm_status s = device_state(&st);
+  if (s != GM_OK) return s;
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return from_hip(e);
+  unsigned long long v = 0;
+  e = hipMemcpy(&v, st->err, sizeof(v), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return from_hip(e);
+  *host_count = static_cast<int64_t>(v);
+  return GM_OK;
+}
+
+gm_status gm_reset_data_errors(hipStream_t stream) {
+  DeviceState* st = nullptr;
+  gm_status s = device_state(&st);
+  if (s != GM_OK) return s;
+  return from_hip(gm::launch_zero_u64(st->err, stream));
+}
+
+gm_status gm_set_option(gm_option opt, int64_t value) {
+  switch (opt) {
+    case GM_OPT_POS_BITS:
+      if (value < 8 || value > 62) return GM_ERR_INVALID_ARG;
+      g_pos_bits = static_cast<int>(value);
+      return GM_OK;
+    case GM_OPT_T0_SCALE_PPM:
+      if (value < 1) return GM_ERR_INVALID_ARG;
+      g_t0_scale = static_cast<double>(value) * 1e-6;
+      return GM_OK;
+    case GM_OPT_MAP_LOAD:
+      if (value < 0 || value > 16) return GM_ERR_INVALID_ARG;
+      g_map_load = static_cast<int>(value);
+      return GM_OK;
+    case GM_OPT_STATS:
+      if (value != 0 && value != 1) return GM_ERR_INVALID_ARG;
+      g_stats = value != 0;
+      return GM_OK;
+    case GM_OPT_REPUBLISH:
+      if (value < 1 || value > 4096 || (value & (value - 1)) != 0) return GM_ERR_INVALID_ARG;
+      g_republish = static_cast<int>(value);
+      return GM_OK;
+  }
+  return GM_ERR_INVALID_ARG;
+}
+
+gm_status gm_get_stats(int64_t* host_counters, int32_t n, hipStream_t stream) {
+  if (!host_counters || n < 1 || n > kStatSlots) return GM_ERR_INVALID_ARG;
+  DeviceState* st = nullptr;
+  gm_status s = device_state(&st);
+  if (s != GM_OK) return s;
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return from_hip(e);
+  unsigned long long v[kStatSlots];
+  e = hipMemcpy(v, st->stats, sizeof(v), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return from_hip(e);
+  for (int i = 0; i < n; ++i) host_counters[i] = static_cast<int64_t>(v[i]);
+  return GM_OK;
+}
+
+gm_status gm_reset_stats(hipStream_t stream) {
+  DeviceState* st = nullptr;
+  gm_status s = device_state(&st);
+  if (s != GM_OK) return s;
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return from_hip(e);
+  return from_hip(hipMemset(st->stats, 0, sizeof(unsigned long long) * kStatSlots));
+}
+
+const char* gm_status_string(gm_status status) {
+  switch (status) {
+    case GM_OK: return "ok";
+    case GM_ERR_INVALID_ARG: return "invalid argument";
+    case GM_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case GM_ERR_DEVICE: return "HIP device error";
+    case GM_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+void gm_release(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (int d = 0; d < kMaxDevices; ++d) {
+    DeviceState& st = g_dev[d];
+    if (!st.err && st.plans.empty()) continue;
+    (void)hipSetDevice(d);
+    if (st.err) (void)hipFree(st.err);
+    if (st.stats) (void)hipFree(st.stats);
+    st.err = nullptr;
+    st.stats = nullptr;
+    for (auto& kv : st.plans) {
+      if (kv.second.list) (void)hipFree(kv.second.list);
+      if (kv.second.plan) (void)hipFree(kv.second.plan);
+    }
+    st.plans.clear();
+  }
+  (void)hipSetDevice(cur);
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// gm_estimators.hip -- estimators and merge on stored sketches.
+//
+//  * Probability-Jaccard estimate (Sec. 1; Theorem 1): fraction of registers
+//    whose Gumbel-ArgMax values agree.  One wave per pair, lanes stride over
+//    the registers (coalesced int32 loads), integer reduction.
+//  * Weighted-cardinality estimate (Sec. 1; Theorem 2): (k-1) / sum_j y_j,
+//    sum taken left to right.  One thread per sketch.
+//  * Merge (Sec. 2.3): registerwise lexicographic (y, s) minimum over r
+//    sketches.  One thread per register.
+#include "gm_common.h"
+
+namespace gm {
+
+__global__ __launch_bounds__(256) void jaccard_kernel(const int32_t* a, const int32_t* b,
+                                                      int64_t npairs, int32_t k, double* out) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
+  for (int64_t pr = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+       pr < npairs; pr += waves) {
+    const int32_t* ra = a + pr * k;
+    const int32_t* rb = b + pr * k;
+    int m = 0;
+    for (int j = lane; j < k; j += kWave) {
+      const int32_t x = ra[j];
+      m += (x == rb[j] && x >= 0) ? 1 : 0;
+    }
+    m = wave_sum_i32(m);
+    if (lane == 0) out[pr] = static_cast<double>(m) / static_cast<double>(k);
+  }
+}
+
+__global__ __launch_bounds__(256) void jaccard_pairs_kernel(const int32_t* store, int64_t nstore,
+                                                            int32_t k, const int64_t* ia,
+                                                            const int64_t* ib, int64_t npairs,
+                                                            double* out,
+                                                            unsigned long long* err) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
+  for (int64_t pr = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+       pr < npairs; pr += waves) {
+    const int64_t x = ia[pr], y = ib[pr];
+    if (x < 0 || x >= nstore || y < 0 || y >= nstore) {
+      if (lane == 0) {
+        out[pr] = bitsd(kNanBits);
+        atomicAdd(err, 1ull);
+      }
+      continue;
+    }
+    const int32_t* ra = store + x * k;
+    const int32_t* rb = store + y * k;
+    int m = 0;
+    for (int j = lane; j < k; j += kWave) {
+      const int32_t u = ra[j];
+      m += (u == rb[j] && u >= 0) ? 1 : 0;
+    }
+    m = wave_sum_i32(m);
+    if (lane == 0) out[pr] = static_cast<double>(m) / static_cast<double>(k);
+  }
+}
+
+__global__ __launch_bounds__(256) void wcard_kernel(const double* val, int64_t nvec, int32_t k,
+                                                    double* out) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < nvec;
+       v += stride) {
+    const double* y = val + v * k;
+    double s = 0.0;
+    for (int32_t j = 0; j < k; ++j) s = s + y[j];
+    out[v] = static_cast<double>(k - 1) / s;
+  }
+}
+
+__global__ __launch_bounds__(256) void merge_kernel(const int32_t* in_idx, const double* in_val,
+                                                    int64_t r, int32_t k, int32_t* out_idx,
+                                                    double* out_val) {
+  const int32_t j = static_cast<int32_t>(static_cast<int64_t>(blockIdx.x) * blockDim.x +
+                                         threadIdx.x);
+  if (j >= k) return;
+  double by = bitsd(kInfBits);
+  int32_t bs = kIdxEmpty;
+  bool poison = false;
+  for (int64_t q = 0; q < r; ++q) {
+    const double y = in_val[q * k + j];
+    const int32_t s = in_idx[q * k + j];
+    if (y != y || s == kIdxPoison) {
+      poison = true;
+      continue;
+    }
+    if (y < by || (y == by && s < bs && s >= 0)) {
+      by = y;
+      bs = s;
+    }
+  }
+  out_idx[j] = poison ? kIdxPoison : bs;
+  out_val[j] = poison ? bitsd(kNanBits) : by;
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
+static unsigned grid_for(int64_t items, int per_block) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > (1 << 20)) g = 1 << 20;
+  return static_cast<unsigned>(g);
+}
+
+hipError_t launch_jaccard(const int32_t* a, const int32_t* b, int64_t npairs, int32_t k,
+                          double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(jaccard_kernel, dim3(grid_for(npairs, 4)), dim3(256), 0, stream, a, b, npairs,
+                     k, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_jaccard_pairs(const int32_t* store, int64_t nstore, int32_t k, const int64_t* ia,
+                                const int64_t* ib, int64_t npairs, double* out,
+                                unsigned long long* err, hipStream_t stream) {
+  hipLaunchKernelGGL(jaccard_pairs_kernel, dim3(grid_for(npairs, 4)), dim3(256), 0, stream, store,
+                     nstore, k, ia, ib, npairs, out, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_wcard(const double* val, int64_t nvec, int32_t k, double* out,
+                        hipStream_t stream) {
+  hipLaunchKernelGGL(wcard_kernel, dim3(grid_for(nvec, 256)), dim3(256), 0, stream, val, nvec, k,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(const int32_t* in_idx, const double* in_val, int64_t r, int32_t k,
+                        int32_t* out_idx, double* out_val, hipStream_t stream) {
+  hipLaunchKernelGGL(merge_kernel, dim3(grid_for(k, 256)), dim3(256), 0, stream, in_idx, in_val, r,
+                     k, out_idx, out_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace gm

@@ -1,0 +1,875 @@
+// gm_fastgm.hip -- FastGM form of the Gumbel-Max sketch on CDNA4.
+//
+// What is computed (Sec. 2.2, Algorithms 1 and 2): every positive element i
+// is a queue that emits its k Exp(v_i) variables in ascending order
+// (t_z = O_z / v_i with O_z = O_{z-1} + E_z / (k - z + 1), Eq. (7)-(8)); the
+// z-th arrival is routed to server pi_i[z] of a Fisher-Yates permutation, and
+// each register keeps the first arrival it receives (lexicographic (t, i)
+// minimum).  An element stops at its first arrival later than the running
+// maximum register y* (FastPrune): its later arrivals are larger still and
+// cannot change any register, so the result equals the unpruned one.
+//
+// GPU mapping.  A planner kernel sorts the vectors into three size classes
+// (and, inside a class, by decreasing size); one persistent kernel per class
+// drains its list through an atomic work counter.  A vector is handled by one
+// workgroup of W waves (W grows with the class) that share its registers:
+//  * Registers live in LDS.  A register is two 64-bit words: `packed` holds
+//    the top bits of the key (positive doubles order like their bit patterns)
+//    above a pos_bits-wide entry position, updated by 64-bit LDS atomic-min;
+//    `fullkey` holds the exact key bits, atomic-min'ed by every arrival that
+//    lowers or ties the packed prefix.  Two different entries whose keys share
+//    the packed prefix raise a per-vector "contest" flag, and the vector's
+//    indices are then resolved exactly by a second walk (see below).
+//  * Threshold: FastSearch's role (guess how far the queues must be released)
+//    is taken by a closed-form time threshold T0 = x_k / sum(v), x_k the
+//    (1 - 1e-4) quantile of the maximum of k Exp(1) variables (Sec. 2.5: the
+//    normalised y* is that maximum).  Each wave republishes
+//    T = min(T0, max_j y_j) every few iterations; registers only decrease, so
+//    any snapshot bounds the final y* from above and pruning stays exact.  If
+//    a register is still empty after the walk (probability 1e-4), the walk is
+//    repeated with a doubled threshold (the repeat re-emits the same
+//    arrivals, and a minimum does not care).
+//  * Probe pass: 64 entries at a time (one per lane, loaded one pass ahead),
+//    every lane draws its element's first arrival; it is offered to its
+//    register, and an element whose first arrival is within T joins the
+//    wave's candidate queue.  This part has no divergence.
+//  * Light path: lanes pop candidates and continue their walks from step 2,
+//    one arrival per lane per iteration.  The Fisher-Yates state of a walk is
+//    the set of displaced positions, kept per lane in a small open-addressing
+//    table in LDS (entries stamped with a per-lane element counter, so a new
+//    element starts with an empty table for free).
+//  * Heavy path: an element whose table fills up is re-walked from its start
+//    by the whole wave: 64 consecutive arrivals are drawn in parallel, the
+//    order-statistic prefix O_z = fma(E_z, c_z, O_{z-1}) is accumulated in
+//    its defined serial order by a chain of DPP lane shifts (lane z holds O_z
+//    after z steps), and the 64 Fisher-Yates swaps are resolved against a
+//    dense LDS permutation by a branch-free pass over the batch's earlier
+//    targets.
+//  * Exact indices on contest: walk again with the exact final y* and, for
+//    every arrival whose key equals its register's final key, atomic-min the
+//    element index into the register.
+#include <utility>
+
+#include "gm_common.h"
+
+namespace gm {
+
+constexpr int kMapSlots = 16;   // per-lane displaced-position table
+constexpr int kHeavyCap = 128;  // per-wave list of elements handed to the segment path
+constexpr int kQueueCap = 64;   // per-wave candidate queue (one probe pass)
+constexpr int kNumClasses = 3;
+constexpr int kPlanBins = 32;   // size sub-bins per class (log2 of n)
+
+struct PlanState {
+  int count[kNumClasses];
+  int offset[kNumClasses];
+  int next[kNumClasses];
+};
+
+struct FastArgs {
+  SketchArgs s;
+  int32_t pos_bits;   // entry-position bits in a packed register
+  double t0_scale;    // multiplies the closed-form threshold (1.0)
+  int32_t map_load;   // table entries per lane before the element goes to the wave path
+  int32_t republish;  // light iterations between threshold republishes (power of two)
+  const int32_t* list;  // planner output: vector ids grouped by class
+  PlanState* plan;
+  int32_t cls;
+  unsigned long long* stats;  // optional counters (nullptr: off)
+};
+
+// Optional per-call counters (summed over the launch), indices:
+enum : int {
+  kStVectors = 0,      // vectors sketched
+  kStIters = 1,        // light-loop wave iterations
+  kStArrivals = 2,     // arrivals drawn on the probe and light paths (lane steps)
+  kStKept = 3,         // of which at or below the threshold
+  kStElements = 4,     // elements continued on the light path
+  kStHeavy = 5,        // elements handed to the segment path
+  kStHeavyBatches = 6, // segment batches (one segment each) of that path
+  kStPasses = 7,       // extra passes after an unfilled register
+  kStResolves = 8,     // exact index resolutions after a contest
+  kStCount = 16
+};
+
+enum : int { kWalkNormal = 0, kWalkResolve = 1 };
+
+struct VecCtx {
+  const int32_t* idx;  // entries of this vector
+  const float* w;
+  int32_t n;
+  int32_t k;
+  uint64_t seed_mix;
+  lds_u64* packed;
+  lds_u64* fullkey;
+  int pos_bits;
+  int mode;
+  lds_i32* contest;
+  int map_load;
+  int republish;
+  unsigned long long* stats;
+};
+
+__device__ __forceinline__ void stat_add(unsigned long long* stats, int which,
+                                         unsigned long long v) {
+  if (stats && v) atomicAdd(&stats[which], v);
+}
+
+__device__ __forceinline__ unsigned long long packed_key(const VecCtx& c, double t, uint32_t pos) {
+  const int B = c.pos_bits;
+  const unsigned long long mask = (1ull << B) - 1ull;
+  return ((dbits(t) >> (B - 1)) << B) | (pos & mask);
+}
+
+// Offer arrival (t, entry pos, index ind) to register srv.  Normal mode
+// returns the packed word the register held before (check it later with
+// contest_check); the exact-key minimum needs no answer.
+__device__ __forceinline__ unsigned long long reg_offer(const VecCtx& c, int32_t srv, double t,
+                                                        unsigned long long pk, int32_t ind) {
+  const unsigned long long tb = dbits(t);
+  if (c.mode == kWalkResolve) {
+    if (tb == c.fullkey[srv])
+      lds_min(&c.packed[srv], static_cast<unsigned long long>(static_cast<uint32_t>(ind)));
+    return ~0ull;
+  }
+  lds_min(&c.fullkey[srv], tb);  // result unused: no wait
+  return lds_min(&c.packed[srv], pk);
+}
+
+// Two different entries whose keys share the packed prefix: the register's
+// index must be resolved exactly.
+__device__ __forceinline__ void contest_check(const VecCtx& c, unsigned long long old,
+                                              unsigned long long pk) {
+  const int B = c.pos_bits;
+  if ((old >> B) == (pk >> B) && old != pk) *c.contest = 1;
+}
+
+__device__ __forceinline__ void reg_update(const VecCtx& c, int32_t srv, double t, uint32_t pos,
+                                           int32_t ind) {
+  const unsigned long long pk = packed_key(c, t, pos);
+  const unsigned long long old = reg_offer(c, srv, t, pk, ind);
+  if (c.mode == kWalkNormal) contest_check(c, old, pk);
+}
+
+// max_j y_j as seen now (+inf while a register is empty).
+__device__ __forceinline__ double wave_max_register(const VecCtx& c) {
+  unsigned long long m = 0;
+  for (int j = __lane_id(); j < c.k; j += kWave) {
+    const unsigned long long x = *reinterpret_cast<volatile lds_u64*>(&c.fullkey[j]);
+    m = x > m ? x : m;
+  }
+  return bitsd(wave_max_u64(m));
+}
+
+// ---------------------------------------------------------------------------
+// Segment path.  An element whose displaced-position table fills up is walked
+// again from its first arrival by a segment of G lanes (G = 16: one DPP row,
+// four elements per wave; G = 64: the whole wave), G consecutive arrivals per
+// batch.  Its permutation is dense in LDS (one u16 per position, tagged with a
+// 3-bit generation so that a stale entry reads as the identity and a new
+// element needs no initialisation).
+
+template <int G>
+__device__ __forceinline__ double seg_shr1(double v, double first) {
+  constexpr int kCtrl = G == 16 ? 0x111 : 0x138;  // row_shr:1 / wave_shr:1
+  const uint64_t b = dbits(v), o = dbits(first);
+  const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(o), static_cast<int>(b), kCtrl, 0xf,
+                                             0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(o >> 32), static_cast<int>(b >> 32),
+                                             kCtrl, 0xf, 0xf, false);
+  return bitsd((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo));
+}
+
+// Value of segment lane L, in every lane of the segment.
+template <int G, int L>
+__device__ __forceinline__ uint32_t seg_bcast(uint32_t x) {
+  if constexpr (G == 16)
+    return static_cast<uint32_t>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x150 + L, 0xf, 0xf, false));
+  else
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), L));
+}
+
+template <int G, int L>
+__device__ __forceinline__ double seg_bcast_f64(double v) {
+  const uint64_t b = dbits(v);
+  const uint32_t lo = seg_bcast<G, L>(static_cast<uint32_t>(b));
+  const uint32_t hi = seg_bcast<G, L>(static_cast<uint32_t>(b >> 32));
+  return bitsd((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Swap step L of a batch: lanes after L see what step L moved (the value it
+// displaced from position z_L now sits at j_L); lanes before L whose target
+// is j_L lose their write.
+template <int G, int L>
+__device__ __forceinline__ void fy_step(int li, int f, int32_t j, int32_t z, uint32_t& cval,
+                                        uint32_t& disp, bool& killed) {
+  const uint32_t dl = seg_bcast<G, L>(disp);
+  const int32_t jl = static_cast<int32_t>(seg_bcast<G, L>(static_cast<uint32_t>(j)));
+  const bool act = L < f;
+  cval = (act && li > L && j == jl) ? dl : cval;
+  disp = (act && li > L && z == jl) ? dl : disp;
+  killed = killed || (act && li < L && j == jl);
+}
+
+template <int G, int... Ls>
+__device__ __forceinline__ void fy_batch(std::integer_sequence<int, Ls...>, int li, int f,
+                                         int32_t j, int32_t z, uint32_t& cval, uint32_t& disp,
+                                         bool& killed) {
+  (fy_step<G, Ls>(li, f, j, z, cval, disp, killed), ...);
+}
+
+template <int G>
+__device__ void segment_walk(const VecCtx& c, const lds_u32* heavy, int nheavy, lds_u16* pm_all,
+                             int pm_stride, uint32_t& hgen, double& T) {
+  const int lane = __lane_id();
+  const int row = lane / G;
+  const int li = lane % G;
+  lds_u16* pm = pm_all + row * pm_stride;
+  const int k = c.k;
+  bool active = false;
+  uint32_t hpos = 0;
+  int32_t ind = 0;
+  double r = 0.0, O = 0.0;
+  uint64_t P = 0;
+  int z0 = 1;
+  int next = 0;
+  int batches = 0, elems = 0;  // per segment (statistics only)
+  int round = 0;               // wave-uniform batch counter
+  while (true) {
+    // idle segments take the next listed elements
+    const uint64_t idle = __ballot(!active && li == 0);
+    if (idle && next < nheavy) {
+      const uint64_t below = row == 0 ? 0ull : (~0ull >> (64 - row * G));
+      const int slot = next + __popcll(idle & below);
+      if (!active && slot < nheavy) {
+        hpos = heavy[slot];
+        ind = c.idx[hpos];
+        r = 1.0 / static_cast<double>(c.w[hpos]);
+        P = mix(c.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(ind)));
+        O = 0.0;
+        z0 = 1;
+        active = true;
+        ++elems;
+        hgen = hgen == 7u ? 1u : hgen + 1u;
+        if (hgen == 1u)
+          for (int q = li; q <= k; q += G) pm[q] = 0;
+      }
+      const int ni = __popcll(idle);
+      next += ni < nheavy - next ? ni : nheavy - next;
+    }
+    if (__ballot(active) == 0) break;
+    const int z = z0 + li;
+    const bool valid = active && z <= k;
+    double E = 0.0, cz = 0.0;
+    int32_t j = z;
+    if (valid) {
+      E = exp1(draw(P, kTagArrival, static_cast<uint32_t>(z)));
+      cz = 1.0 / static_cast<double>(k - z + 1);
+      j = randint(draw(P, kTagShuffle, static_cast<uint32_t>(z)), z, k);
+    }
+    // O_z = fma(E_z, c_z, O_{z-1}) in its defined order: after step i lanes
+    // 0..i of the segment hold their final value.
+    double Ol = fma(E, cz, O);
+#pragma unroll
+    for (int i = 1; i < G; ++i) Ol = fma(E, cz, seg_shr1<G>(Ol, O));
+    const double t = Ol * r;
+    const uint64_t stopm = __ballot(valid && t > T);
+    const uint64_t validm = __ballot(valid);
+    const uint64_t rmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+    const uint64_t rs = (stopm >> (row * G)) & rmask;
+    const int nval = __popcll((validm >> (row * G)) & rmask);
+    const int f = rs ? __ffsll(static_cast<long long>(rs)) - 1 : nval;
+    uint32_t cval = 0, disp = 0;
+    if (li < f) {
+      const uint32_t ej = pm[j], ez = pm[z];
+      cval = (ej >> 13) == hgen ? (ej & 0x1FFFu) : static_cast<uint32_t>(j);
+      disp = (ez >> 13) == hgen ? (ez & 0x1FFFu) : static_cast<uint32_t>(z);
+    }
+    bool killed = false;
+    fy_batch<G>(std::make_integer_sequence<int, G>{}, li, f, j, z, cval, disp, killed);
+    if (li < f && !killed) pm[j] = static_cast<uint16_t>((hgen << 13) | disp);
+    if (li < f) reg_update(c, static_cast<int32_t>(cval) - 1, t, hpos, ind);
+    const bool finished = f < nval || z0 + G > k;
+    O = seg_bcast_f64<G, G - 1>(Ol);
+    if (active) {
+      ++batches;
+      if (finished)
+        active = false;
+      else
+        z0 += G;
+    }
+    // the republish is a wave-wide reduction: keep its condition wave-uniform
+    if (c.mode == kWalkNormal && (++round & 3) == 0) T = fmin(T, wave_max_register(c));
+  }
+  if (c.stats) {
+    const int e2 = wave_sum_i32(li == 0 ? elems : 0);
+    const int b2 = wave_sum_i32(li == 0 ? batches : 0);
+    if (lane == 0) {
+      stat_add(c.stats, kStHeavy, static_cast<unsigned long long>(e2));
+      stat_add(c.stats, kStHeavyBatches, static_cast<unsigned long long>(b2));
+    }
+  }
+}
+
+// Per-lane displaced-position table: entry = stamp:8 | (pos-1):12 | (val-1):12,
+// slot s of this lane at mp[s * kWave], home slot (pos-1) mod kMapSlots,
+// linear probing.  map_resolve continues a lookup of position p whose home
+// entry `e` was already read: returns the value at p (p if not displaced);
+// `slot` receives p's slot or the first free slot of its probe chain (-1 if
+// the table is full), `found` whether p was present.
+__device__ __forceinline__ uint32_t map_resolve(const lds_u32* mp, uint32_t stamp, uint32_t p,
+                                                uint32_t e, int& slot, bool& found) {
+  const uint32_t key = p - 1;
+  int s = static_cast<int>(key & (kMapSlots - 1));
+  found = false;
+  for (int q = 0; q < kMapSlots; ++q) {
+    if ((e >> 24) != stamp) {
+      slot = s;
+      return p;
+    }
+    if (((e >> 12) & 0xFFFu) == key) {
+      slot = s;
+      found = true;
+      return (e & 0xFFFu) + 1;
+    }
+    s = (s + 1) & (kMapSlots - 1);
+    e = mp[s * kWave];
+  }
+  slot = -1;
+  return p;
+}
+
+// Candidate queue of one wave: elements whose first arrival passed the
+// threshold, waiting for a lane to continue their walk (structure of arrays).
+struct Queue {
+  lds_u64* P;
+  lds_f64* r;
+  lds_f64* O;
+  lds_u32* pos;
+  lds_i32* ind;
+  lds_u32* j1;
+};
+
+__host__ __device__ constexpr size_t queue_bytes() { return kQueueCap * (8 + 8 + 8 + 4 + 4 + 4); }
+
+// One wave's share of a walk over the vector's entries.  Each iteration:
+//  (a) while the queue has room, a uniform probe pass takes the next 64
+//      entries (one per lane): hash prefix, 1/v, first arrival; the first
+//      arrival is offered to its register (step 1 of the permutation swaps
+//      position 1 with j_1, so it goes to server j_1) and, if it is within
+//      the threshold, the element joins the queue;
+//  (b) lanes without an element pop one from the queue and continue its walk
+//      from step 2; every active lane draws one arrival.
+// Elements whose displaced-position table fills up are listed in `heavy`
+// and walked on the segment path when the list is nearly full or at the end.
+template <int G>
+__device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, lds_u32* heavy,
+                          lds_u16* pm, int pm_stride, uint32_t& hgen, lds_u32* mp,
+                          uint32_t& stamp, const Queue& q) {
+  const int lane = __lane_id();
+  const double c1 = 1.0 / static_cast<double>(c.k);
+  bool have = false;
+  uint32_t pos = 0;
+  int32_t ind = 0;
+  double r = 0.0, O = 0.0;
+  uint64_t P = 0;
+  int32_t z = 0;
+  int32_t entries = 0;
+  int qhead = 0, qtail = 0;   // wave-uniform ring counters
+  int nheavy = 0;             // wave-uniform heavy-list length
+  int iter = 0;
+  // contest check deferred by one iteration (hides the atomic's latency)
+  bool pend = false;
+  unsigned long long pend_old = 0, pend_pk = 0;
+  // entries of the next probe pass, loaded one pass ahead
+  int pbase = 0;
+  if (lane == 0) pbase = lds_add(cursor, kWave);
+  pbase = readlane_i32(pbase, 0);
+  bool more = pbase < c.n;    // entries left to probe
+  float pf_w = 0.0f;
+  int32_t pf_i = 0;
+  if (pbase + lane < c.n) {
+    pf_w = c.w[pbase + lane];
+    pf_i = c.idx[pbase + lane];
+  }
+  unsigned arrivals = 0, kept = 0, started = 0;
+  while (true) {
+    // (a) probe pass
+    if (more && kQueueCap - (qtail - qhead) >= kWave) {
+      const int e = pbase + lane;
+      const float wv = pf_w;
+      const int32_t pi = pf_i;
+      int nb = 0;
+      if (lane == 0) nb = lds_add(cursor, kWave);
+      pbase = readlane_i32(nb, 0);
+      if (pbase + lane < c.n) {
+        pf_w = c.w[pbase + lane];
+        pf_i = c.idx[pbase + lane];
+      }
+      bool keep = false;
+      uint64_t pP = 0;
+      double pr = 0.0, pO = 0.0;
+      int32_t pj = 1;
+      if (e < c.n && wv > 0.0f) {
+        pP = mix(c.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(pi)));
+        pr = 1.0 / static_cast<double>(wv);
+        pO = fma(exp1(draw(pP, kTagArrival, 1u)), c1, 0.0);
+        const double t = pO * pr;
+        ++arrivals;
+        if (t <= T) {
+          ++kept;
+          pj = randint(draw(pP, kTagShuffle, 1u), 1, c.k);
+          reg_update(c, pj - 1, t, static_cast<uint32_t>(e), pi);
+          keep = c.k > 1;
+        }
+      }
+      const uint64_t km = __ballot(keep);
+      if (keep) {
+        const int slot = (qtail + __popcll(km & lanemask_lt())) & (kQueueCap - 1);
+        q.P[slot] = pP;
+        q.r[slot] = pr;
+        q.O[slot] = pO;
+        q.pos[slot] = static_cast<uint32_t>(e);
+        q.ind[slot] = pi;
+        q.j1[slot] = static_cast<uint32_t>(pj);
+      }
+      qtail += __popcll(km);
+      more = pbase < c.n;
+    }
+    // (b) refill idle lanes from the queue
+    const uint64_t need = __ballot(!have);
+    const int avail = qtail - qhead;
+    if (need && avail > 0) {
+      if (!have) {
+        const int rank = __popcll(need & lanemask_lt());
+        if (rank < avail) {
+          const int slot = (qhead + rank) & (kQueueCap - 1);
+          P = q.P[slot];
+          r = q.r[slot];
+          O = q.O[slot];
+          pos = q.pos[slot];
+          ind = q.ind[slot];
+          const uint32_t j1 = q.j1[slot];
+          if (O * r <= T) {
+            have = true;
+            z = 1;
+            ++started;
+            stamp = stamp + 1;
+            if (stamp == 256u) {
+              for (int s = 0; s < kMapSlots; ++s) mp[s * kWave] = 0u;
+              stamp = 1u;
+            }
+            // after step 1, position j1 holds value 1
+            entries = 0;
+            if (j1 != 1u) {
+              mp[((j1 - 1) & (kMapSlots - 1)) * kWave] = (stamp << 24) | ((j1 - 1) << 12);
+              entries = 1;
+            }
+          }
+        }
+      }
+      const int npop = __popcll(need);
+      qhead += npop < avail ? npop : avail;
+    }
+    const bool any_have = __ballot(have) != 0;
+    const bool done = !any_have && !more && qtail == qhead;
+    bool overflow = false;
+    if (any_have) {
+      if (have) {
+        ++z;
+        const double E = exp1(draw(P, kTagArrival, static_cast<uint32_t>(z)));
+        O = fma(E, 1.0 / static_cast<double>(c.k - z + 1), O);
+        const double t = O * r;
+        ++arrivals;
+        if (pend) contest_check(c, pend_old, pend_pk);
+        pend = false;
+        if (t > T) {
+          have = false;
+        } else {
+          ++kept;
+          const int32_t j = randint(draw(P, kTagShuffle, static_cast<uint32_t>(z)), z, c.k);
+          // home slots of z and j read together, chains followed only on collision
+          const uint32_t ez = mp[((z - 1) & (kMapSlots - 1)) * kWave];
+          const uint32_t ej = mp[((j - 1) & (kMapSlots - 1)) * kWave];
+          int zslot, jslot;
+          bool zfound, jfound;
+          const uint32_t vz = map_resolve(mp, stamp, static_cast<uint32_t>(z), ez, zslot, zfound);
+          const uint32_t vj = map_resolve(mp, stamp, static_cast<uint32_t>(j), ej, jslot, jfound);
+          if (j != z) {
+            if (jslot < 0 || (!jfound && entries >= c.map_load)) {
+              overflow = true;
+            } else {
+              mp[jslot * kWave] =
+                  (stamp << 24) | (static_cast<uint32_t>(j - 1) << 12) | (vz - 1);
+              entries += jfound ? 0 : 1;
+            }
+          }
+          if (overflow) {
+            have = false;
+          } else {
+            pend_pk = packed_key(c, t, pos);
+            pend_old = reg_offer(c, static_cast<int32_t>(vj) - 1, t, pend_pk, ind);
+            pend = c.mode == kWalkNormal;
+            if (z == c.k) have = false;
+          }
+        }
+      }
+      ++iter;
+      if (c.mode == kWalkNormal && (iter & (c.republish - 1)) == 0)
+        T = fmin(T, wave_max_register(c));
+    }
+    const uint64_t om = __ballot(overflow);
+    if (overflow) heavy[nheavy + __popcll(om & lanemask_lt())] = pos;
+    nheavy += __popcll(om);
+    if (done && pend) {
+      contest_check(c, pend_old, pend_pk);
+      pend = false;
+    }
+    if (done || nheavy > kHeavyCap - kWave) {
+      segment_walk<G>(c, heavy, nheavy, pm, pm_stride, hgen, T);
+      nheavy = 0;
+    }
+    if (done) break;
+  }
+  if (c.stats) {
+    const int a = wave_sum_i32(static_cast<int>(arrivals));
+    const int kk = wave_sum_i32(static_cast<int>(kept));
+    const int st = wave_sum_i32(static_cast<int>(started));
+    if (lane == 0) {
+      stat_add(c.stats, kStIters, static_cast<unsigned long long>(iter));
+      stat_add(c.stats, kStArrivals, static_cast<unsigned long long>(a));
+      stat_add(c.stats, kStKept, static_cast<unsigned long long>(kk));
+      stat_add(c.stats, kStElements, static_cast<unsigned long long>(st));
+    }
+  }
+}
+
+// (1 - p) quantile of the maximum of k Exp(1) variables, p = 1e-4.
+__device__ __forceinline__ double max_exp_quantile(int k) {
+  const double p = 1e-4;
+  return -log(-expm1(log1p(-p) / static_cast<double>(k)));
+}
+
+__host__ __device__ constexpr int perm_stride(int k_max) { return ((k_max + 1 + 3) / 4) * 4; }
+
+// Lanes per segment of the segment path: 16 (four elements per wave) while
+// four dense permutations stay small, else the whole wave.
+__host__ __device__ constexpr int segment_lanes(int k_max) { return k_max <= 2048 ? 16 : 64; }
+
+__host__ __device__ constexpr size_t wave_lds_bytes(int k_max) {
+  return queue_bytes() + static_cast<size_t>(kMapSlots) * kWave * 4 +
+         static_cast<size_t>(kWave / segment_lanes(k_max)) * perm_stride(k_max) * 2 +
+         kHeavyCap * 4;
+}
+
+size_t fastgm_lds_bytes(int k_max, int waves) {
+  return 16 * static_cast<size_t>(k_max) + waves * wave_lds_bytes(k_max);
+}
+
+struct FgShared {
+  int cursor;
+  int contest;
+  int bad;
+  int task;
+  double wsum[16];
+  unsigned long long wmax[16];
+};
+
+template <int W, int G>
+__device__ void sketch_vector(const FastArgs& fa, int64_t v, FgShared& sh, lds_u64* packed,
+                              lds_u64* fullkey, lds_u16* pm, int pm_stride, uint32_t& hgen,
+                              lds_u32* heavy, lds_u32* mp, uint32_t& stamp, const Queue& q) {
+  constexpr int kBlock = W * kWave;
+  const SketchArgs& p = fa.s;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const VecDesc d = vec_desc(p, v);
+  const int32_t span = out_span(p, v, d);
+  const int64_t n64 = d.b - d.a;
+  const bool bad0 = d.bad || n64 > 0x7FFFFFFF;
+  if (tid == 0) {
+    sh.bad = bad0 ? 1 : 0;
+    sh.contest = 0;
+    sh.cursor = 0;
+  }
+  if (!bad0) {
+    for (int j = tid; j < d.k; j += kBlock) {
+      packed[j] = ~0ull;
+      fullkey[j] = kInfBits;
+    }
+  }
+  __syncthreads();
+  // Validation and the mass S = sum(v) (its rounding only moves T0).
+  double part = 0.0;
+  bool badl = false;
+  if (!bad0) {
+    for (int64_t e = d.a + tid; e < d.b; e += kBlock) {
+      const int32_t i = p.idx[e];
+      const float wv = p.w[e];
+      if (i < 0 || !weight_valid(wv))
+        badl = true;
+      else
+        part += static_cast<double>(wv);
+    }
+  }
+  if (badl) sh.bad = 1;
+  part = wave_sum_f64(part);
+  if (lane == 0) sh.wsum[wave] = part;
+  __syncthreads();
+  double S = 0.0;
+  for (int qq = 0; qq < W; ++qq) S += sh.wsum[qq];
+  if (sh.bad || !(S > 0.0)) {
+    const bool bad = sh.bad != 0;
+    for (int j = tid; j < span; j += kBlock) {
+      p.out_idx[d.o + j] = bad ? kIdxPoison : kIdxEmpty;
+      p.out_val[d.o + j] = bitsd(bad ? kNanBits : kInfBits);
+    }
+    if (bad && tid == 0) atomicAdd(p.err, 1ull);
+    __syncthreads();
+    return;
+  }
+
+  VecCtx c;
+  c.idx = p.idx + d.a;
+  c.w = p.w + d.a;
+  c.n = static_cast<int32_t>(n64);
+  c.k = d.k;
+  c.seed_mix = p.seed_mix;
+  c.packed = packed;
+  c.fullkey = fullkey;
+  c.pos_bits = fa.pos_bits;
+  c.mode = kWalkNormal;
+  c.contest = (lds_i32*)(&sh.contest);  // address-space cast of a __shared__ object
+  c.map_load = fa.map_load;
+  c.republish = fa.republish;
+  c.stats = fa.stats;
+  if (tid == 0) stat_add(fa.stats, kStVectors, 1);
+  // Positions that do not fit the packed word: resolve indices exactly.
+  if (tid == 0 && n64 >= (1ll << fa.pos_bits)) sh.contest = 1;
+  lds_i32* cursor = (lds_i32*)(&sh.cursor);
+
+  // Walk with the closed-form threshold; repeat with a larger one while a
+  // register is empty; then, if two entries tied on a packed prefix, walk
+  // once more to resolve the indices exactly.  One call site keeps a single
+  // copy of the walk in the kernel.
+  double T = max_exp_quantile(d.k) * fa.t0_scale / S;
+  bool resolve = false;
+  for (int pass = 0;; ++pass) {
+    walk_wave<G>(c, cursor, T, heavy, pm, pm_stride, hgen, mp, stamp, q);
+    __syncthreads();
+    if (resolve) break;
+    bool miss = false;
+    for (int j = tid; j < d.k; j += kBlock) miss |= fullkey[j] == kInfBits;
+    if (__syncthreads_or(miss)) {
+      if (tid == 0) stat_add(fa.stats, kStPasses, 1);
+      T = pass >= 8 ? bitsd(kInfBits) : T * 2.0;
+      if (tid == 0) sh.cursor = 0;
+      __syncthreads();
+      continue;
+    }
+    if (sh.contest == 0) break;
+    // exact indices: walk again with the exact y*, keeping the index of every
+    // arrival that equals its register's final key
+    resolve = true;
+    if (tid == 0) stat_add(fa.stats, kStResolves, 1);
+    unsigned long long m = 0;
+    for (int j = tid; j < d.k; j += kBlock) m = fullkey[j] > m ? fullkey[j] : m;
+    m = wave_max_u64(m);
+    if (lane == 0) sh.wmax[wave] = m;
+    __syncthreads();
+    unsigned long long ystar = 0;
+    for (int qq = 0; qq < W; ++qq) ystar = sh.wmax[qq] > ystar ? sh.wmax[qq] : ystar;
+    for (int j = tid; j < d.k; j += kBlock) packed[j] = ~0ull;
+    if (tid == 0) sh.cursor = 0;
+    __syncthreads();
+    c.mode = kWalkResolve;
+    T = bitsd(ystar);
+  }
+  const unsigned long long pmask = (1ull << fa.pos_bits) - 1ull;
+  for (int j = tid; j < d.k; j += kBlock) {
+    const unsigned long long pk = packed[j];
+    p.out_idx[d.o + j] = resolve ? static_cast<int32_t>(pk) : c.idx[pk & pmask];
+    p.out_val[d.o + j] = bitsd(fullkey[j]);
+  }
+  __syncthreads();
+}
+
+// Persistent kernel of one size class: workgroups of W waves pull vector ids
+// from the class list until it is exhausted.
+template <int W, int G>
+__global__ __launch_bounds__(W * kWave) void fastgm_class_kernel(FastArgs fa) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  __shared__ FgShared sh;
+  const int k_max = fa.s.k_max;
+  GM_LDS unsigned char* base = (GM_LDS unsigned char*)(dyn);  // address-space cast
+  lds_u64* packed = reinterpret_cast<lds_u64*>(base);
+  lds_u64* fullkey = packed + k_max;
+  GM_LDS unsigned char* wave_base = reinterpret_cast<GM_LDS unsigned char*>(fullkey + k_max) +
+                                    (threadIdx.x / kWave) * wave_lds_bytes(k_max);
+  Queue q;
+  q.P = reinterpret_cast<lds_u64*>(wave_base);
+  q.r = reinterpret_cast<lds_f64*>(wave_base + kQueueCap * 8);
+  q.O = reinterpret_cast<lds_f64*>(wave_base + kQueueCap * 16);
+  q.pos = reinterpret_cast<lds_u32*>(wave_base + kQueueCap * 24);
+  q.ind = reinterpret_cast<lds_i32*>(wave_base + kQueueCap * 28);
+  q.j1 = reinterpret_cast<lds_u32*>(wave_base + kQueueCap * 32);
+  GM_LDS unsigned char* rest = wave_base + queue_bytes();
+  lds_u32* mp_base = reinterpret_cast<lds_u32*>(rest);
+  lds_u16* pm = reinterpret_cast<lds_u16*>(rest + kMapSlots * kWave * 4);
+  const int pm_stride = perm_stride(k_max);
+  const int pm_bytes = (kWave / G) * pm_stride * 2;
+  lds_u32* heavy = reinterpret_cast<lds_u32*>(rest + kMapSlots * kWave * 4 + pm_bytes);
+  const int lane = threadIdx.x % kWave;
+  lds_u32* mp = mp_base + lane;
+  for (int s = 0; s < kMapSlots; ++s) mp[s * kWave] = 0u;
+  for (int q2 = lane; q2 < (kWave / G) * pm_stride; q2 += kWave) pm[q2] = 0;
+  uint32_t stamp = 0;
+  uint32_t hgen = 0;
+
+  const PlanState* plan = fa.plan;
+  const int count = plan->count[fa.cls];
+  const int32_t* list = fa.list + plan->offset[fa.cls];
+  int* next = &fa.plan->next[fa.cls];
+  for (;;) {
+    if (threadIdx.x == 0) sh.task = atomicAdd(next, 1);
+    __syncthreads();
+    const int t = sh.task;
+    __syncthreads();
+    if (t >= count) break;
+    sketch_vector<W, G>(fa, list[t], sh, packed, fullkey, pm, pm_stride, hgen, heavy, mp, stamp,
+                        q);
+  }
+}
+
+// Planner: one workgroup sorts the vector ids by (size class, decreasing
+// log2 size) with a counting sort, and resets the classes' work counters.
+constexpr int kPlanBlock = 1024;
+
+__device__ __forceinline__ int plan_bin(const SketchArgs& p, int64_t v, int64_t lim_s,
+                                        int64_t lim_m) {
+  const int64_t n = p.off[v + 1] - p.off[v];
+  const int cls = n <= lim_s ? 0 : (n <= lim_m ? 1 : 2);
+  const int lg = n > 0 ? 63 - __clzll(static_cast<unsigned long long>(n)) : 0;
+  return cls * kPlanBins + (kPlanBins - 1 - (lg < kPlanBins ? lg : kPlanBins - 1));
+}
+
+__global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t* list,
+                                                          PlanState* plan, int64_t lim_s,
+                                                          int64_t lim_m) {
+  __shared__ int hist[kNumClasses * kPlanBins];
+  __shared__ int base[kNumClasses * kPlanBins];
+  const int tid = threadIdx.x;
+  for (int b = tid; b < kNumClasses * kPlanBins; b += kPlanBlock) hist[b] = 0;
+  __syncthreads();
+  for (int64_t v = tid; v < p.nvec; v += kPlanBlock) atomicAdd(&hist[plan_bin(p, v, lim_s, lim_m)], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int b = 0; b < kNumClasses * kPlanBins; ++b) {
+      base[b] = acc;
+      acc += hist[b];
+    }
+    for (int c = 0; c < kNumClasses; ++c) {
+      plan->offset[c] = base[c * kPlanBins];
+      int cnt = 0;
+      for (int b = 0; b < kPlanBins; ++b) cnt += hist[c * kPlanBins + b];
+      plan->count[c] = cnt;
+      plan->next[c] = 0;
+    }
+  }
+  __syncthreads();
+  for (int64_t v = tid; v < p.nvec; v += kPlanBlock) {
+    const int b = plan_bin(p, v, lim_s, lim_m);
+    list[atomicAdd(&base[b], 1)] = static_cast<int32_t>(v);
+  }
+}
+
+// Waves per workgroup of each size class: small vectors get one wave unless
+// the register array is large enough that waves should share it; limited by
+// LDS (160 KB per CU).
+int class_waves(int cls, int k_max) {
+  int want = cls == 0 ? 1 : (cls == 1 ? 4 : 8);
+  if (cls == 0 && k_max > 512) want = k_max > 2048 ? 4 : 2;
+  int w = want;
+  while (w > 1 && fastgm_lds_bytes(k_max, w) + sizeof(FgShared) > 160 * 1024) w /= 2;
+  return w;
+}
+
+struct OccKey {
+  const void* fn;
+  size_t lds;
+  int per_cu;
+};
+
+template <int W, int G>
+static hipError_t launch_class(const FastArgs& fa, int cus, hipStream_t stream) {
+  const size_t lds = fastgm_lds_bytes(fa.s.k_max, W);
+  const void* fn = reinterpret_cast<const void*>(fastgm_class_kernel<W, G>);
+  // occupancy per (kernel, LDS size), computed once
+  static OccKey cache[64];
+  static int ncache = 0;
+  int per_cu = 0;
+  for (int i = 0; i < ncache; ++i)
+    if (cache[i].fn == fn && cache[i].lds == lds) per_cu = cache[i].per_cu;
+  if (per_cu == 0) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, W * kWave, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    if (ncache < 64) cache[ncache++] = OccKey{fn, lds, per_cu};
+  }
+  int64_t grid = static_cast<int64_t>(cus) * per_cu;
+  if (grid > fa.s.nvec) grid = fa.s.nvec;
+  hipLaunchKernelGGL((fastgm_class_kernel<W, G>), dim3(static_cast<unsigned>(grid)), dim3(W * kWave),
+                     lds, stream, fa);
+  return hipGetLastError();
+}
+
+template <int G>
+static hipError_t launch_class_w(const FastArgs& fa, int waves, int cus, hipStream_t stream) {
+  switch (waves) {
+    case 1: return launch_class<1, G>(fa, cus, stream);
+    case 2: return launch_class<2, G>(fa, cus, stream);
+    case 4: return launch_class<4, G>(fa, cus, stream);
+    default: return launch_class<8, G>(fa, cus, stream);
+  }
+}
+
+// Vectors of at most kLimS entries go one per wave; up to kLimM four waves
+// share one; larger ones take the widest workgroup that fits.
+constexpr int64_t kLimS = 2048;
+constexpr int64_t kLimM = 32768;
+
+hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
+                         int republish, int32_t* list, void* plan, int cus,
+                         unsigned long long* stats, hipStream_t stream) {
+  FastArgs fa;
+  fa.stats = stats;
+  fa.s = s;
+  fa.pos_bits = pos_bits;
+  fa.t0_scale = t0_scale;
+  fa.map_load = map_load;
+  fa.republish = republish;
+  fa.list = list;
+  fa.plan = static_cast<PlanState*>(plan);
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, stream, s, list, fa.plan, kLimS,
+                     kLimM);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int cls = 0; cls < kNumClasses; ++cls) {
+    fa.cls = cls;
+    const int waves = class_waves(cls, s.k_max);
+    e = segment_lanes(s.k_max) == 16 ? launch_class_w<16>(fa, waves, cus, stream)
+                                     : launch_class_w<64>(fa, waves, cus, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+size_t plan_state_bytes() { return sizeof(PlanState); }
+
+}  // namespace gm

@@ -1,0 +1,81 @@
+"""The C ABI without a GPU: the library loads, exports every symbol that
+include/gm.h declares, and rejects bad arguments on the host before touching
+a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2302_05176_amd import _native, build
+    if not build.up_to_date():
+        build.build(force=True)
+    return _native.load()
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "gm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    syms = declared_symbols()
+    for s in ("gm_sketch", "gm_sketch_plain", "gm_sketch_batched", "gm_jaccard_est",
+              "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_get_data_errors",
+              "gm_release"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+
+
+def test_host_side_argument_validation(lib):
+    from paper_2302_05176_amd import _native as N
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)
+    u = ctypes.c_uint64(1)
+    # nvec < 0, k out of range, null pointers: rejected before any device call
+    assert lib.gm_sketch(fake, fake, fake, -1, 8, u, fake, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_sketch(fake, fake, fake, 1, 0, u, fake, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_sketch(fake, fake, fake, 1, 4097, u, fake, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_sketch(nul, fake, fake, 1, 8, u, fake, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_sketch_plain(fake, fake, fake, 1, 8, u, nul, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_sketch_batched(fake, fake, fake, 1, nul, fake, 8, u, 0, fake, fake,
+                                 nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_sketch_batched(fake, fake, fake, 1, fake, fake, 8, u, 7, fake, fake,
+                                 nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_wcard_est(fake, 1, 1, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_jaccard_est(fake, fake, -1, 8, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_jaccard_est_pairs(fake, 1, 8, nul, fake, 1, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_merge(fake, fake, 0, 8, fake, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_get_data_errors(None, nul) == N.GM_ERR_INVALID_ARG
+    # empty work is a no-op
+    assert lib.gm_sketch(nul, nul, nul, 0, 8, u, nul, nul, nul) == N.GM_OK
+    assert lib.gm_jaccard_est(nul, nul, 0, 8, nul, nul) == N.GM_OK
+
+
+def test_options_validation(lib):
+    from paper_2302_05176_amd import _native as N
+    assert lib.gm_set_option(0, 7) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_set_option(2, 17) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_set_option(3, 3) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_set_option(99, 1) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_set_option(0, 24) == N.GM_OK
+    assert lib.gm_set_option(3, 4) == N.GM_OK
+    assert lib.gm_status_string(1) == b"invalid argument"
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2302_05176_amd import _native, build
+    monkeypatch.setattr(build, "LIB", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_native, "_lib", None)
+    with pytest.raises(ImportError):
+        _native.load()

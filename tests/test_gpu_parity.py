@@ -1,0 +1,264 @@
+"""GPU parity: the HIP kernels against the CPU oracle, element by element.
+
+Register indices must match bit for bit; register values are compared bit
+for bit too (the draw specification is a fixed sequence of IEEE operations,
+so both sides compute identical doubles; the stated tolerance of 1e-15
+relative is therefore met with zero error).  Estimates are compared bit for
+bit as well (same operations, same order).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_05176_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gm():
+    import paper_2302_05176_amd as gm
+    from paper_2302_05176_amd import build
+    if not build.up_to_date():
+        build.build(force=True)
+    assert torch.cuda.is_available()
+    gm.reset_options()
+    yield gm
+    gm.reset_options()
+
+
+DEV = "cuda:0"
+
+
+def _gpu_sketch(gm, idx, w, off, k, seed, form="fastgm"):
+    ti = torch.from_numpy(np.ascontiguousarray(idx, np.int32)).to(DEV)
+    tw = torch.from_numpy(np.ascontiguousarray(w, np.float32)).to(DEV)
+    to = torch.from_numpy(np.ascontiguousarray(off, np.int64)).to(DEV)
+    s, y = gm.sketch(ti, tw, to, k, seed, form=form)
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), y.cpu().numpy()
+
+
+def _assert_same(got, want, what=""):
+    gs, gy = got
+    ws, wy = want
+    bad = np.argwhere(gs != ws)
+    assert bad.size == 0, f"{what}: {len(bad)} index mismatches, first at {bad[:3].tolist()}"
+    gb = np.ascontiguousarray(gy).view(np.uint64)
+    wb = np.ascontiguousarray(wy).view(np.uint64)
+    badv = np.argwhere(gb != wb)
+    assert badv.size == 0, f"{what}: {len(badv)} value mismatches, first at {badv[:3].tolist()}"
+
+
+def test_single_vector_both_forms(gm):
+    idx, w, off = W.single(nplus=1000)
+    for form, of in (("fastgm", oracle.FORM_STREAM), ("plain", oracle.FORM_PLAIN)):
+        print(f"single vector n+=1000 k=128 form={form}", flush=True)
+        _assert_same(_gpu_sketch(gm, idx, w, off, 128, 1, form),
+                     oracle.sketch(idx, w, off, 128, 1, form=of), form)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 7, 64, 256, 1000, 4096])
+def test_fastgm_mixed_batch(gm, k):
+    max_n = 3000 if k <= 256 else 800
+    idx, w, off = W.mixed(seed=200 + k, nvec=48, max_n=max_n)
+    print(f"mixed batch k={k}", flush=True)
+    _assert_same(_gpu_sketch(gm, idx, w, off, k, 17 + k),
+                 oracle.sketch(idx, w, off, k, 17 + k, form=oracle.FORM_STREAM), f"k={k}")
+
+
+@pytest.mark.parametrize("k", [1, 5, 64, 300])
+def test_plain_mixed_batch(gm, k):
+    idx, w, off = W.mixed(seed=300 + k, nvec=32, max_n=1200)
+    print(f"plain mixed batch k={k}", flush=True)
+    _assert_same(_gpu_sketch(gm, idx, w, off, k, 5, "plain"),
+                 oracle.sketch(idx, w, off, k, 5, form=oracle.FORM_PLAIN), f"plain k={k}")
+
+
+def test_document_batch_k256(gm):
+    idx, w, off = W.batch(nvec=400, seed=1202)
+    oracle.set_threads(8)
+    print("document batch 400 vectors k=256 fastgm", flush=True)
+    _assert_same(_gpu_sketch(gm, idx, w, off, 256, 1),
+                 oracle.sketch(idx, w, off, 256, 1, form=oracle.FORM_STREAM), "batch fastgm")
+    print("document batch 60 vectors k=256 plain", flush=True)
+    o2 = off[:61]
+    _assert_same(_gpu_sketch(gm, idx, w, o2, 256, 1, "plain"),
+                 oracle.sketch(idx, w, o2, 256, 1, form=oracle.FORM_PLAIN), "batch plain")
+
+
+@pytest.mark.parametrize("opt,val", [("pos_bits", 60), ("pos_bits", 40), ("map_load", 0),
+                                     ("map_load", 2), ("map_load", 16), ("t0_scale_ppm", 1),
+                                     ("t0_scale_ppm", 100_000), ("republish", 1),
+                                     ("republish", 64)])
+def test_forced_internal_paths(gm, opt, val):
+    """Debug knobs force packed-prefix contests (exact re-resolution), the
+    wave-cooperative heavy path, the enlarge-and-repeat fallback and other
+    threshold schedules; none may change the sketch."""
+    idx, w, off = W.mixed(seed=404, nvec=40, max_n=1500)
+    try:
+        gm.set_option(opt, val)
+        for k in (16, 512):
+            print(f"forced {opt}={val} k={k}", flush=True)
+            _assert_same(_gpu_sketch(gm, idx, w, off, k, 9),
+                         oracle.sketch(idx, w, off, k, 9, form=oracle.FORM_STREAM),
+                         f"{opt}={val} k={k}")
+    finally:
+        gm.reset_options()
+
+
+def test_heavy_single_elements_large_k(gm):
+    rows_i, rows_w = [], []
+    rng = np.random.default_rng(9)
+    for n in (1, 2, 3, 10, 50):
+        rows_i.append(np.sort(rng.choice(1 << 24, n, replace=False)))
+        ww = rng.lognormal(0, 2, size=n).astype(np.float32)
+        rows_w.append(ww)
+    idx, w, off = W._pack(rows_i, rows_w)
+    for k in (4096, 2049):
+        print(f"heavy small vectors k={k}", flush=True)
+        _assert_same(_gpu_sketch(gm, idx, w, off, k, 3),
+                     oracle.sketch(idx, w, off, k, 3, form=oracle.FORM_STREAM), f"k={k}")
+
+
+def test_poisoned_vectors_and_error_counter(gm):
+    idx = np.array([1, 2, 3, 4, 5, -6, 7, 8, 9, 10], np.int32)
+    w = np.array([1, np.nan, 1, -2, 1, 1, np.inf, 1, 0, 2], np.float32)
+    # rows: NaN weight, negative weight, negative index, inf weight, decreasing
+    # offsets, and an overlapping row that again holds -6 and inf
+    off = np.array([0, 2, 4, 6, 7, 5, 10], np.int64)
+    gm.reset_data_errors()
+    for form, of in (("fastgm", oracle.FORM_STREAM), ("plain", oracle.FORM_PLAIN)):
+        got = _gpu_sketch(gm, idx, w, off, 32, 1, form)
+        want = oracle.sketch(idx, w, off, 32, 1, form=of)
+        assert np.array_equal(got[0], want[0])
+        assert np.array_equal(np.isnan(got[1]), np.isnan(want[1]))
+        fin = ~np.isnan(want[1])
+        assert np.array_equal(got[1][fin].view(np.uint64), want[1][fin].view(np.uint64))
+        assert np.all(got[0] == -2)          # every row holds a bad entry or bad offsets
+    assert gm.get_data_errors() == 2 * 6
+    gm.reset_data_errors()
+    assert gm.get_data_errors() == 0
+
+
+def test_empty_inputs(gm):
+    # nvec = 0: nothing launched
+    z = torch.zeros(0, dtype=torch.int32, device=DEV)
+    s, y = gm.sketch(z, z.float(), torch.zeros(1, dtype=torch.int64, device=DEV), 8, 1)
+    assert s.shape == (0, 8)
+    # empty rows and all-zero rows
+    idx = np.array([4, 5], np.int32)
+    w = np.array([0.0, 0.0], np.float32)
+    off = np.array([0, 0, 2, 2], np.int64)
+    for form in ("fastgm", "plain"):
+        s, y = _gpu_sketch(gm, idx, w, off, 64, 1, form)
+        assert np.all(s == -1) and np.all(np.isinf(y))
+
+
+def test_invalid_arguments_rejected(gm):
+    t = torch.zeros(4, dtype=torch.int32, device=DEV)
+    off = torch.tensor([0, 4], dtype=torch.int64, device=DEV)
+    with pytest.raises(gm.GMError):
+        gm.sketch(t, t.float(), off, 0, 1)
+    with pytest.raises(gm.GMError):
+        gm.sketch(t, t.float(), off, gm.GM_K_MAX + 1, 1)
+
+
+def test_batched_mixed_k(gm):
+    idx, w, off, kk = W.uneven(nvec=120, seed=77, size_cap=2500)
+    outoff = np.zeros(len(kk) + 1, np.int64)
+    np.cumsum(kk, out=outoff[1:])
+    t = lambda a: torch.from_numpy(a).to(DEV)
+    for form, of in (("fastgm", oracle.FORM_STREAM),):
+        print(f"batched mixed k form={form}", flush=True)
+        s, y = gm.sketch_batched(t(idx), t(w), t(off), t(kk), t(outoff), int(kk.max()), 11,
+                                 form=form)
+        torch.cuda.synchronize()
+        s, y = s.cpu().numpy(), y.cpu().numpy()
+        for kv in np.unique(kk):
+            vs = np.nonzero(kk == kv)[0]
+            rows_i = [idx[off[v]:off[v + 1]] for v in vs]
+            rows_w = [w[off[v]:off[v + 1]] for v in vs]
+            si, sw, so = W._pack(rows_i, rows_w)
+            ws, wy = oracle.sketch(si, sw, so, int(kv), 11, form=of)
+            gs = np.stack([s[outoff[v]:outoff[v + 1]] for v in vs])
+            gy = np.stack([y[outoff[v]:outoff[v + 1]] for v in vs])
+            _assert_same((gs, gy), (ws, wy), f"k={kv}")
+
+
+def test_batched_plain_small(gm):
+    idx, w, off, kk = W.uneven(nvec=24, seed=78, size_cap=400, ks=(8, 64, 200))
+    outoff = np.zeros(len(kk) + 1, np.int64)
+    np.cumsum(kk, out=outoff[1:])
+    t = lambda a: torch.from_numpy(a).to(DEV)
+    s, y = gm.sketch_batched(t(idx), t(w), t(off), t(kk), t(outoff), 200, 12, form="plain")
+    torch.cuda.synchronize()
+    s, y = s.cpu().numpy(), y.cpu().numpy()
+    for v in range(len(kk)):
+        ws, wy = oracle.sketch(idx[off[v]:off[v + 1]], w[off[v]:off[v + 1]],
+                               np.array([0, off[v + 1] - off[v]]), int(kk[v]), 12,
+                               form=oracle.FORM_PLAIN)
+        _assert_same((s[outoff[v]:outoff[v + 1]][None], y[outoff[v]:outoff[v + 1]][None]),
+                     (ws, wy), f"v={v}")
+
+
+def test_estimators_match_oracle(gm):
+    idx, w, off, frac = W.pairs(npairs=200, seed=31)
+    k = 256
+    s, y = _gpu_sketch(gm, idx, w, off, k, 2)
+    a = torch.from_numpy(s[0::2].copy()).to(DEV)
+    b = torch.from_numpy(s[1::2].copy()).to(DEV)
+    J = gm.jaccard_est(a, b).cpu().numpy()
+    Jo = np.array([oracle.jaccard(s[2 * p], s[2 * p + 1]) for p in range(200)])
+    assert np.array_equal(J.view(np.uint64), Jo.view(np.uint64))
+    C = gm.wcard_est(torch.from_numpy(y).to(DEV)).cpu().numpy()
+    Co = np.array([oracle.wcard(y[v]) for v in range(len(y))])
+    assert np.array_equal(C.view(np.uint64), Co.view(np.uint64))
+    # store lookups, including out-of-range rows
+    store = torch.from_numpy(s).to(DEV)
+    ia = torch.tensor([0, 2, 5, -1, 10**6], dtype=torch.int64, device=DEV)
+    ib = torch.tensor([1, 3, 5, 0, 1], dtype=torch.int64, device=DEV)
+    gm.reset_data_errors()
+    Jp = gm.jaccard_est_pairs(store, ia, ib).cpu().numpy()
+    assert Jp[0] == Jo[0] and Jp[1] == Jo[1] and Jp[2] == 1.0
+    assert np.isnan(Jp[3]) and np.isnan(Jp[4])
+    assert gm.get_data_errors() == 2
+    gm.reset_data_errors()
+
+
+def test_merge_equals_sketch_of_union(gm):
+    idx, w, off = W.batch(nvec=1, seed=55, sizes=np.array([3000]))
+    k = 512
+    whole = _gpu_sketch(gm, idx, w, off, k, 4)
+    parts_off = np.array([0, 1000, 1700, 3000], np.int64)
+    ps, py = _gpu_sketch(gm, idx, w, parts_off, k, 4)
+    mi, mv = gm.merge(torch.from_numpy(ps).to(DEV), torch.from_numpy(py).to(DEV))
+    _assert_same((mi.cpu().numpy()[None], mv.cpu().numpy()[None]), whole, "merge")
+
+
+def test_order_and_duplicates_do_not_change_result(gm):
+    idx, w, off = W.batch(nvec=20, seed=61)
+    base = _gpu_sketch(gm, idx, w, off, 128, 6)
+    rng = np.random.default_rng(1)
+    rows_i, rows_w = [], []
+    for v in range(20):
+        ii, ww = idx[off[v]:off[v + 1]], w[off[v]:off[v + 1]]
+        dup = rng.integers(0, len(ii), size=len(ii) // 2)
+        ii = np.concatenate([ii, ii[dup]])
+        ww = np.concatenate([ww, ww[dup]])
+        p = rng.permutation(len(ii))
+        rows_i.append(ii[p])
+        rows_w.append(ww[p])
+    i2, w2, o2 = W._pack(rows_i, rows_w)
+    _assert_same(_gpu_sketch(gm, i2, w2, o2, 128, 6), base, "shuffled+dups")
+    _assert_same(_gpu_sketch(gm, idx, w, off, 128, 6), base, "repeat")
+
+
+def test_long_vector_sampled(gm):
+    idx, w, off = W.stream(nplus=1_000_000, seed=1003)
+    for k in (1024, 4096):
+        print(f"long vector n+=1e6 k={k}", flush=True)
+        _assert_same(_gpu_sketch(gm, idx, w, off, k, 1),
+                     oracle.sketch(idx, w, off, k, 1, form=oracle.FORM_STREAM), f"k={k}")
