@@ -183,6 +183,13 @@ gm_status gm_reset_data_errors(hipStream_t stream);
  *                        together (0 sends almost every element there).
  *   GM_OPT_REPUBLISH     [4] light iterations between republishes of the
  *                        running maximum register, a power of two.
+ *   GM_OPT_SEG_REST      [16] an element whose expected number of further
+ *                        arrivals below the threshold (k v_i (T - t_1))
+ *                        exceeds this goes to the segment path straight
+ *                        from its first arrival, 0..1000000 (0: every
+ *                        continuing element does).
+ *   GM_OPT_SMALL_WAVES   [0] waves that share one small vector (0: chosen
+ *                        from k; else 1, 2, 4 or 8).
  *   GM_OPT_STATS         [0] 1 makes FastGM calls accumulate work counters
  *                        (read them with gm_get_stats); costs a few atomics
  *                        per vector.
@@ -193,7 +200,9 @@ typedef enum {
     GM_OPT_T0_SCALE_PPM = 1,
     GM_OPT_MAP_LOAD = 2,
     GM_OPT_REPUBLISH = 3,
-    GM_OPT_STATS = 4
+    GM_OPT_STATS = 4,
+    GM_OPT_SEG_REST = 5,
+    GM_OPT_SMALL_WAVES = 6
 } gm_option;
 gm_status gm_set_option(gm_option opt, int64_t value);
 

@@ -169,7 +169,8 @@ def reset_data_errors(stream=None) -> None:
 
 
 def set_option(name: str, value: int) -> None:
-    """Tuning/testing knobs of gm_set_option: pos_bits, t0_scale_ppm, map_load, republish."""
+    """Tuning/testing knobs of gm_set_option: pos_bits, t0_scale_ppm, map_load, republish,
+    stats, seg_rest."""
     L = _native.load()
     _native.check(L.gm_set_option(_native.OPTIONS[name], int(value)), f"gm_set_option({name})")
 
@@ -189,7 +190,8 @@ def reset_stats(stream=None) -> None:
 
 def reset_options() -> None:
     for name, v in (("pos_bits", 24), ("t0_scale_ppm", 1_000_000), ("map_load", 10),
-                    ("republish", 4), ("stats", 0)):
+                    ("republish", 4), ("stats", 0), ("seg_rest", 16),
+                    ("small_waves", 0)):
         set_option(name, v)
 
 

@@ -21,7 +21,8 @@ GM_FORM_PLAIN = 1
 
 GM_K_MAX = 4096
 
-OPTIONS = {"pos_bits": 0, "t0_scale_ppm": 1, "map_load": 2, "republish": 3, "stats": 4}
+OPTIONS = {"pos_bits": 0, "t0_scale_ppm": 1, "map_load": 2, "republish": 3, "stats": 4,
+           "seg_rest": 5, "small_waves": 6}
 STATS = ["vectors", "iterations", "arrivals", "kept", "elements", "heavy", "heavy_batches",
          "passes", "resolves"]
 

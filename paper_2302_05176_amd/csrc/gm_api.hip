@@ -13,9 +13,11 @@
 namespace gm {
 hipError_t launch_plain(const SketchArgs& p, hipStream_t stream);
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
-                         int republish, int32_t* list, void* plan, int cus,
+                         int republish, double seg_rest, int small_waves, int32_t* list,
+                         void* plan, void* big, int32_t* pool, int64_t pool_cap, int cus,
                          unsigned long long* stats, hipStream_t stream);
 size_t plan_state_bytes();
+size_t big_info_bytes();
 hipError_t launch_jaccard(const int32_t* a, const int32_t* b, int64_t npairs, int32_t k,
                           double* out, hipStream_t stream);
 hipError_t launch_jaccard_pairs(const int32_t* store, int64_t nstore, int32_t k, const int64_t* ia,
@@ -34,10 +36,16 @@ constexpr int kMaxDevices = 64;
 
 // Planner workspace of one (device, stream): the vector list and the class
 // counters.  Keyed by stream so that calls on different streams never share it.
+// Candidate-list pool of the big vectors (entries): 128 MiB.  A big vector
+// that does not fit is walked over all of its entries instead.
+constexpr int64_t kPoolCap = 32ll << 20;
+
 struct PlanWorkspace {
   int32_t* list = nullptr;
+  void* big = nullptr;   // one BigInfo per vector slot
   int64_t cap = 0;
   void* plan = nullptr;
+  int32_t* pool = nullptr;
 };
 
 constexpr int kStatSlots = 16;
@@ -57,6 +65,8 @@ int g_pos_bits = 24;
 double g_t0_scale = 1.0;
 int g_map_load = 10;
 int g_republish = 4;
+double g_seg_rest = 16.0;
+int g_small_waves = 0;
 bool g_stats = false;
 
 gm_status from_hip(hipError_t e) {
@@ -105,15 +115,23 @@ gm_status plan_workspace(DeviceState* st, hipStream_t stream, int64_t nvec, Plan
   if (!ws.plan) {
     hipError_t e = hipMalloc(&ws.plan, gm::plan_state_bytes());
     if (e != hipSuccess) return from_hip(e);
+    void* q = nullptr;
+    e = hipMalloc(&q, sizeof(int32_t) * static_cast<size_t>(kPoolCap));
+    if (e != hipSuccess) return from_hip(e);
+    ws.pool = static_cast<int32_t*>(q);
   }
   if (ws.cap < nvec) {
     if (ws.list) (void)hipFree(ws.list);
+    if (ws.big) (void)hipFree(ws.big);
     ws.list = nullptr;
+    ws.big = nullptr;
     ws.cap = 0;
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, sizeof(int32_t) * static_cast<size_t>(nvec));
     if (e != hipSuccess) return from_hip(e);
     ws.list = static_cast<int32_t*>(p);
+    e = hipMalloc(&ws.big, gm::big_info_bytes() * static_cast<size_t>(nvec));
+    if (e != hipSuccess) return from_hip(e);
     ws.cap = nvec;
   }
   *out = &ws;
@@ -149,8 +167,10 @@ gm_status sketch_common(const int32_t* indices, const float* weights, const int6
   PlanWorkspace* ws = nullptr;
   s = plan_workspace(st, stream, nvec, &ws);
   if (s != GM_OK) return s;
-  return from_hip(gm::launch_fastgm(a, g_pos_bits, g_t0_scale, g_map_load, g_republish, ws->list,
-                                    ws->plan, st->cus, g_stats ? st->stats : nullptr, stream));
+  return from_hip(gm::launch_fastgm(a, g_pos_bits, g_t0_scale, g_map_load, g_republish,
+                                    g_seg_rest, g_small_waves, ws->list, ws->plan, ws->big,
+                                    ws->pool, kPoolCap, st->cus,
+                                    g_stats ? st->stats : nullptr, stream));
 }
 
 }  // namespace
@@ -253,6 +273,15 @@ gm_status gm_set_option(gm_option opt, int64_t value) {
       if (value < 0 || value > 16) return GM_ERR_INVALID_ARG;
       g_map_load = static_cast<int>(value);
       return GM_OK;
+    case GM_OPT_SEG_REST:
+      if (value < 0 || value > 1000000) return GM_ERR_INVALID_ARG;
+      g_seg_rest = static_cast<double>(value);
+      return GM_OK;
+    case GM_OPT_SMALL_WAVES:
+      if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+        return GM_ERR_INVALID_ARG;
+      g_small_waves = static_cast<int>(value);
+      return GM_OK;
     case GM_OPT_STATS:
       if (value != 0 && value != 1) return GM_ERR_INVALID_ARG;
       g_stats = value != 0;
@@ -313,7 +342,9 @@ void gm_release(void) {
     st.stats = nullptr;
     for (auto& kv : st.plans) {
       if (kv.second.list) (void)hipFree(kv.second.list);
+      if (kv.second.big) (void)hipFree(kv.second.big);
       if (kv.second.plan) (void)hipFree(kv.second.plan);
+      if (kv.second.pool) (void)hipFree(kv.second.pool);
     }
     st.plans.clear();
   }

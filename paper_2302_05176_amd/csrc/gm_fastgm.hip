@@ -57,13 +57,45 @@ namespace gm {
 constexpr int kMapSlots = 16;   // per-lane displaced-position table
 constexpr int kHeavyCap = 128;  // per-wave list of elements handed to the segment path
 constexpr int kQueueCap = 64;   // per-wave candidate queue (one probe pass)
-constexpr int kNumClasses = 3;
+// Vectors are grouped by size class (small, medium, big) and k class
+// (k <= 256, 1024, 2048, 4096) so that each persistent kernel sizes its LDS
+// for its own k range.  Class id = size_class * kKClasses + k_class; the big
+// classes (size class 2) are contiguous in the planner's list.
+constexpr int kSizeClasses = 3;
+constexpr int kKClasses = 4;
+constexpr int kNumClasses = kSizeClasses * kKClasses;
+constexpr int kBigFirst = 2 * kKClasses;
+
+__host__ __device__ constexpr int kclass_hi(int kc) { return kc == 0 ? 256 : (kc == 1 ? 1024 : (kc == 2 ? 2048 : 4096)); }
+
+__host__ __device__ inline int kclass_of(int32_t k) {
+  return k <= 256 ? 0 : (k <= 1024 ? 1 : (k <= 2048 ? 2 : 3));
+}
 constexpr int kPlanBins = 32;   // size sub-bins per class (log2 of n)
 
 struct PlanState {
   int count[kNumClasses];
   int offset[kNumClasses];
   int next[kNumClasses];
+  int64_t big_chunks;   // chunks of kBigChunk entries over all big vectors
+};
+
+// Vectors above kLimM entries ("big") are prepared by two grid-wide passes
+// before their workgroup walks them: one validates and sums the weights, the
+// other draws every entry's first arrival and keeps, in a candidate list,
+// the entries whose first arrival is within the closed-form threshold T0.
+// Only those can reach a register once y* <= T0 (an element's arrivals only
+// grow), so the walk visits the candidates instead of the whole vector.
+constexpr int64_t kBigChunk = 65536;
+
+struct BigInfo {
+  int64_t chunk_base;    // first chunk of this vector
+  int64_t cand_off;      // offset of its candidate list in the pool
+  double S;              // sum of weights (grid-wide atomic sum)
+  int bad;               // invalid entry seen
+  int cand_count;        // candidates found (may exceed cand_cap)
+  int cand_cap;          // room in the pool (0: no list, walk everything)
+  int pad;
 };
 
 struct FastArgs {
@@ -72,9 +104,14 @@ struct FastArgs {
   double t0_scale;    // multiplies the closed-form threshold (1.0)
   int32_t map_load;   // table entries per lane before the element goes to the wave path
   int32_t republish;  // light iterations between threshold republishes (power of two)
+  double seg_rest;    // expected remaining arrivals above which a probe goes to the segment path
   const int32_t* list;  // planner output: vector ids grouped by class
   PlanState* plan;
+  BigInfo* big;         // per big vector, in class-list order
+  int32_t* pool;        // candidate lists of the big vectors
+  int64_t pool_cap;
   int32_t cls;
+  int32_t lds_k;        // register-array size this launch's LDS is laid out for
   unsigned long long* stats;  // optional counters (nullptr: off)
 };
 
@@ -97,7 +134,8 @@ enum : int { kWalkNormal = 0, kWalkResolve = 1 };
 struct VecCtx {
   const int32_t* idx;  // entries of this vector
   const float* w;
-  int32_t n;
+  const int32_t* gather;  // walk these positions only (nullptr: all entries)
+  int32_t n;              // entries (or candidates) to walk
   int32_t k;
   uint64_t seed_mix;
   lds_u64* packed;
@@ -107,6 +145,7 @@ struct VecCtx {
   lds_i32* contest;
   int map_load;
   int republish;
+  double seg_rest;
   unsigned long long* stats;
 };
 
@@ -389,29 +428,34 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, lds_u32* h
   bool more = pbase < c.n;    // entries left to probe
   float pf_w = 0.0f;
   int32_t pf_i = 0;
+  int32_t pf_p = pbase + lane;
   if (pbase + lane < c.n) {
-    pf_w = c.w[pbase + lane];
-    pf_i = c.idx[pbase + lane];
+    if (c.gather) pf_p = c.gather[pbase + lane];
+    pf_w = c.w[pf_p];
+    pf_i = c.idx[pf_p];
   }
   unsigned arrivals = 0, kept = 0, started = 0;
   while (true) {
     // (a) probe pass
     if (more && kQueueCap - (qtail - qhead) >= kWave) {
-      const int e = pbase + lane;
+      const bool inb = pbase + lane < c.n;
+      const int e = pf_p;          // position in the vector
       const float wv = pf_w;
       const int32_t pi = pf_i;
       int nb = 0;
       if (lane == 0) nb = lds_add(cursor, kWave);
       pbase = readlane_i32(nb, 0);
+      pf_p = pbase + lane;
       if (pbase + lane < c.n) {
-        pf_w = c.w[pbase + lane];
-        pf_i = c.idx[pbase + lane];
+        if (c.gather) pf_p = c.gather[pbase + lane];
+        pf_w = c.w[pf_p];
+        pf_i = c.idx[pf_p];
       }
-      bool keep = false;
+      bool keep = false, seg = false;
       uint64_t pP = 0;
       double pr = 0.0, pO = 0.0;
       int32_t pj = 1;
-      if (e < c.n && wv > 0.0f) {
+      if (inb && wv > 0.0f) {
         pP = mix(c.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(pi)));
         pr = 1.0 / static_cast<double>(wv);
         pO = fma(exp1(draw(pP, kTagArrival, 1u)), c1, 0.0);
@@ -421,9 +465,17 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, lds_u32* h
           ++kept;
           pj = randint(draw(pP, kTagShuffle, 1u), 1, c.k);
           reg_update(c, pj - 1, t, static_cast<uint32_t>(e), pi);
-          keep = c.k > 1;
+          // Arrivals still to come before T arrive at rate about k v: a walk
+          // expected to outgrow the lane's table goes to the segment path now.
+          const bool longwalk =
+              static_cast<double>(c.k) * static_cast<double>(wv) * (T - t) > c.seg_rest;
+          seg = c.k > 1 && longwalk;
+          keep = c.k > 1 && !longwalk;
         }
       }
+      const uint64_t sm = __ballot(seg);
+      if (seg) heavy[nheavy + __popcll(sm & lanemask_lt())] = static_cast<uint32_t>(e);
+      nheavy += __popcll(sm);
       const uint64_t km = __ballot(keep);
       if (keep) {
         const int slot = (qtail + __popcll(km & lanemask_lt())) & (kQueueCap - 1);
@@ -436,6 +488,10 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, lds_u32* h
       }
       qtail += __popcll(km);
       more = pbase < c.n;
+      if (nheavy > kHeavyCap - kWave) {
+        segment_walk<G>(c, heavy, nheavy, pm, pm_stride, hgen, T);
+        nheavy = 0;
+      }
     }
     // (b) refill idle lanes from the queue
     const uint64_t need = __ballot(!have);
@@ -577,9 +633,10 @@ struct FgShared {
 };
 
 template <int W, int G>
-__device__ void sketch_vector(const FastArgs& fa, int64_t v, FgShared& sh, lds_u64* packed,
-                              lds_u64* fullkey, lds_u16* pm, int pm_stride, uint32_t& hgen,
-                              lds_u32* heavy, lds_u32* mp, uint32_t& stamp, const Queue& q) {
+__device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, FgShared& sh,
+                              lds_u64* packed, lds_u64* fullkey, lds_u16* pm, int pm_stride,
+                              uint32_t& hgen, lds_u32* heavy, lds_u32* mp, uint32_t& stamp,
+                              const Queue& q) {
   constexpr int kBlock = W * kWave;
   const SketchArgs& p = fa.s;
   const int tid = threadIdx.x;
@@ -601,10 +658,16 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, FgShared& sh, lds_u
     }
   }
   __syncthreads();
-  // Validation and the mass S = sum(v) (its rounding only moves T0).
+  // Validation and the mass S = sum(v) (its rounding only moves T0); a big
+  // vector had both done by the grid-wide pass.
   double part = 0.0;
   bool badl = false;
-  if (!bad0) {
+  if (bi) {
+    if (tid == 0) {
+      part = bi->S;
+      badl = bi->bad != 0;
+    }
+  } else if (!bad0) {
     for (int64_t e = d.a + tid; e < d.b; e += kBlock) {
       const int32_t i = p.idx[e];
       const float wv = p.w[e];
@@ -634,7 +697,12 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, FgShared& sh, lds_u
   VecCtx c;
   c.idx = p.idx + d.a;
   c.w = p.w + d.a;
+  c.gather = nullptr;
   c.n = static_cast<int32_t>(n64);
+  if (bi && bi->cand_cap > 0 && bi->cand_count <= bi->cand_cap) {
+    c.gather = fa.pool + bi->cand_off;
+    c.n = bi->cand_count;
+  }
   c.k = d.k;
   c.seed_mix = p.seed_mix;
   c.packed = packed;
@@ -644,6 +712,7 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, FgShared& sh, lds_u
   c.contest = (lds_i32*)(&sh.contest);  // address-space cast of a __shared__ object
   c.map_load = fa.map_load;
   c.republish = fa.republish;
+  c.seg_rest = fa.seg_rest;
   c.stats = fa.stats;
   if (tid == 0) stat_add(fa.stats, kStVectors, 1);
   // Positions that do not fit the packed word: resolve indices exactly.
@@ -665,6 +734,9 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, FgShared& sh, lds_u
     if (__syncthreads_or(miss)) {
       if (tid == 0) stat_add(fa.stats, kStPasses, 1);
       T = pass >= 8 ? bitsd(kInfBits) : T * 2.0;
+      // above T0 the candidate list no longer covers every element
+      c.gather = nullptr;
+      c.n = static_cast<int32_t>(n64);
       if (tid == 0) sh.cursor = 0;
       __syncthreads();
       continue;
@@ -702,7 +774,7 @@ template <int W, int G>
 __global__ __launch_bounds__(W * kWave) void fastgm_class_kernel(FastArgs fa) {
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ FgShared sh;
-  const int k_max = fa.s.k_max;
+  const int k_max = fa.lds_k;
   GM_LDS unsigned char* base = (GM_LDS unsigned char*)(dyn);  // address-space cast
   lds_u64* packed = reinterpret_cast<lds_u64*>(base);
   lds_u64* fullkey = packed + k_max;
@@ -738,8 +810,11 @@ __global__ __launch_bounds__(W * kWave) void fastgm_class_kernel(FastArgs fa) {
     const int t = sh.task;
     __syncthreads();
     if (t >= count) break;
-    sketch_vector<W, G>(fa, list[t], sh, packed, fullkey, pm, pm_stride, hgen, heavy, mp, stamp,
-                        q);
+    const BigInfo* bi =
+        (fa.cls >= kBigFirst && fa.big) ? &fa.big[plan->offset[fa.cls] - plan->offset[kBigFirst] + t]
+                                        : nullptr;
+    sketch_vector<W, G>(fa, list[t], bi, sh, packed, fullkey, pm, pm_stride, hgen, heavy, mp,
+                        stamp, q);
   }
 }
 
@@ -750,14 +825,18 @@ constexpr int kPlanBlock = 1024;
 __device__ __forceinline__ int plan_bin(const SketchArgs& p, int64_t v, int64_t lim_s,
                                         int64_t lim_m) {
   const int64_t n = p.off[v + 1] - p.off[v];
-  const int cls = n <= lim_s ? 0 : (n <= lim_m ? 1 : 2);
+  const int32_t k = p.kvec ? p.kvec[v] : p.k_uniform;
+  const int sc = n <= lim_s ? 0 : (n <= lim_m ? 1 : 2);
+  const int kc = (k >= 1 && k <= p.k_max) ? kclass_of(k) : 0;
+  const int cls = sc * kKClasses + kc;
   const int lg = n > 0 ? 63 - __clzll(static_cast<unsigned long long>(n)) : 0;
   return cls * kPlanBins + (kPlanBins - 1 - (lg < kPlanBins ? lg : kPlanBins - 1));
 }
 
 __global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t* list,
-                                                          PlanState* plan, int64_t lim_s,
-                                                          int64_t lim_m) {
+                                                          PlanState* plan, BigInfo* big,
+                                                          int64_t pool_cap, double t0_scale,
+                                                          int64_t lim_s, int64_t lim_m) {
   __shared__ int hist[kNumClasses * kPlanBins];
   __shared__ int base[kNumClasses * kPlanBins];
   const int tid = threadIdx.x;
@@ -784,14 +863,176 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t*
     const int b = plan_bin(p, v, lim_s, lim_m);
     list[atomicAdd(&base[b], 1)] = static_cast<int32_t>(v);
   }
+  __syncthreads();
+  // Big vectors: chunk ranges and candidate-list room, by exclusive scans.
+  __shared__ int64_t sc_ch[kPlanBlock];
+  __shared__ int64_t sc_cap[kPlanBlock];
+  __shared__ int64_t run_ch, run_cap;
+  int c2 = 0;
+  for (int cc = kBigFirst; cc < kNumClasses; ++cc) c2 += plan->count[cc];
+  const int32_t* list2 = list + plan->offset[kBigFirst];
+  if (tid == 0) {
+    run_ch = 0;
+    run_cap = 0;
+  }
+  __syncthreads();
+  for (int b0 = 0; b0 < c2; b0 += kPlanBlock) {
+    const int i = b0 + tid;
+    int64_t nch = 0, cap = 0;
+    if (i < c2) {
+      const int64_t v = list2[i];
+      const int64_t n = p.off[v + 1] - p.off[v];
+      const int32_t k = p.kvec ? p.kvec[v] : p.k_uniform;
+      nch = (n + kBigChunk - 1) / kBigChunk;
+      if (k >= 1 && k <= p.k_max) {
+        const double x = static_cast<double>(k) * max_exp_quantile(k) * (t0_scale > 1.0 ? t0_scale : 1.0);
+        const int64_t c = static_cast<int64_t>(1.25 * x + 4.0 * sqrt(x) + 256.0);
+        cap = c < n ? c : n;
+      }
+    }
+    sc_ch[tid] = nch;
+    sc_cap[tid] = cap;
+    __syncthreads();
+    for (int d = 1; d < kPlanBlock; d <<= 1) {
+      const int64_t a1 = tid >= d ? sc_ch[tid - d] : 0;
+      const int64_t a2 = tid >= d ? sc_cap[tid - d] : 0;
+      __syncthreads();
+      sc_ch[tid] += a1;
+      sc_cap[tid] += a2;
+      __syncthreads();
+    }
+    if (i < c2) {
+      BigInfo bi;
+      bi.chunk_base = run_ch + sc_ch[tid] - nch;
+      bi.cand_off = run_cap + sc_cap[tid] - cap;
+      bi.S = 0.0;
+      bi.bad = 0;
+      bi.cand_count = 0;
+      bi.cand_cap = (bi.cand_off + cap <= pool_cap) ? static_cast<int>(cap) : 0;
+      bi.pad = 0;
+      big[i] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      run_ch += sc_ch[kPlanBlock - 1];
+      run_cap += sc_cap[kPlanBlock - 1];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) plan->big_chunks = run_ch;
+}
+
+// Big vector owning chunk t (largest b with chunk_base <= t).
+__device__ __forceinline__ int big_of_chunk(const BigInfo* big, int c2, int64_t t) {
+  int lo = 0, hi = c2 - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (big[mid].chunk_base <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+constexpr int kBigBlock = 256;
+
+// Grid-wide pass 1 over big vectors: validate entries, sum weights.
+__global__ __launch_bounds__(kBigBlock) void big_sum_kernel(FastArgs fa) {
+  __shared__ double ws[kBigBlock / kWave];
+  __shared__ int sbad;
+  const SketchArgs& p = fa.s;
+  int c2 = 0;
+  for (int cc = kBigFirst; cc < kNumClasses; ++cc) c2 += fa.plan->count[cc];
+  const int32_t* list2 = fa.list + fa.plan->offset[kBigFirst];
+  const int64_t total = fa.plan->big_chunks;
+  const int tid = threadIdx.x;
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int b = big_of_chunk(fa.big, c2, t);
+    const VecDesc d = vec_desc(p, list2[b]);
+    if (d.bad) continue;
+    const int64_t e0 = d.a + (t - fa.big[b].chunk_base) * kBigChunk;
+    const int64_t e1 = e0 + kBigChunk < d.b ? e0 + kBigChunk : d.b;
+    if (tid == 0) sbad = 0;
+    double part = 0.0;
+    bool badl = false;
+    for (int64_t e = e0 + tid; e < e1; e += kBigBlock) {
+      const int32_t i = p.idx[e];
+      const float wv = p.w[e];
+      if (i < 0 || !weight_valid(wv))
+        badl = true;
+      else
+        part += static_cast<double>(wv);
+    }
+    __syncthreads();
+    if (badl) sbad = 1;
+    part = wave_sum_f64(part);
+    if (tid % kWave == 0) ws[tid / kWave] = part;
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int q = 0; q < kBigBlock / kWave; ++q) tot += ws[q];
+      atomicAdd(&fa.big[b].S, tot);
+      if (sbad) atomicOr(&fa.big[b].bad, 1);
+    }
+    __syncthreads();
+  }
+}
+
+// Grid-wide pass 2 over big vectors: first arrival of every entry; entries
+// within T0 go to the vector's candidate list.
+__global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
+  const SketchArgs& p = fa.s;
+  int c2 = 0;
+  for (int cc = kBigFirst; cc < kNumClasses; ++cc) c2 += fa.plan->count[cc];
+  const int32_t* list2 = fa.list + fa.plan->offset[kBigFirst];
+  const int64_t total = fa.plan->big_chunks;
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave;
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int b = big_of_chunk(fa.big, c2, t);
+    const VecDesc d = vec_desc(p, list2[b]);
+    BigInfo* bi = &fa.big[b];
+    if (d.bad || bi->bad || !(bi->S > 0.0) || bi->cand_cap <= 0) continue;
+    const double T0 = max_exp_quantile(d.k) * fa.t0_scale / bi->S;
+    const double c1 = 1.0 / static_cast<double>(d.k);
+    const int64_t e0 = d.a + (t - bi->chunk_base) * kBigChunk;
+    const int64_t e1 = e0 + kBigChunk < d.b ? e0 + kBigChunk : d.b;
+    for (int64_t eb = e0; eb < e1; eb += kBigBlock) {
+      const int64_t e = eb + tid;
+      bool cand = false;
+      if (e < e1) {
+        const float wv = p.w[e];
+        if (wv > 0.0f) {
+          const int32_t i = p.idx[e];
+          const uint64_t P = mix(p.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(i)));
+          const double r = 1.0 / static_cast<double>(wv);
+          const double O1 = fma(exp1(draw(P, kTagArrival, 1u)), c1, 0.0);
+          cand = O1 * r <= T0;
+        }
+      }
+      const uint64_t m = __ballot(cand);
+      if (m) {
+        const int leader = __ffsll(static_cast<long long>(m)) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&bi->cand_count, __popcll(m));
+        base = readlane_i32(base, leader);
+        if (cand) {
+          const int slot = base + __popcll(m & lanemask_lt());
+          if (slot < bi->cand_cap) fa.pool[bi->cand_off + slot] = static_cast<int32_t>(e - d.a);
+        }
+      }
+    }
+  }
 }
 
 // Waves per workgroup of each size class: small vectors get one wave unless
 // the register array is large enough that waves should share it; limited by
 // LDS (160 KB per CU).
-int class_waves(int cls, int k_max) {
-  int want = cls == 0 ? 1 : (cls == 1 ? 4 : 8);
-  if (cls == 0 && k_max > 512) want = k_max > 2048 ? 4 : 2;
+int class_waves(int sc, int k_max, int small_waves) {
+  int want = sc == 0 ? 1 : (sc == 1 ? 4 : 8);
+  if (sc == 0 && k_max > 512) want = k_max > 2048 ? 4 : 2;
+  if (sc == 0 && small_waves > 0) want = small_waves;
   int w = want;
   while (w > 1 && fastgm_lds_bytes(k_max, w) + sizeof(FgShared) > 160 * 1024) w /= 2;
   return w;
@@ -805,7 +1046,7 @@ struct OccKey {
 
 template <int W, int G>
 static hipError_t launch_class(const FastArgs& fa, int cus, hipStream_t stream) {
-  const size_t lds = fastgm_lds_bytes(fa.s.k_max, W);
+  const size_t lds = fastgm_lds_bytes(fa.lds_k, W);
   const void* fn = reinterpret_cast<const void*>(fastgm_class_kernel<W, G>);
   // occupancy per (kernel, LDS size), computed once
   static OccKey cache[64];
@@ -845,10 +1086,15 @@ constexpr int64_t kLimS = 2048;
 constexpr int64_t kLimM = 32768;
 
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
-                         int republish, int32_t* list, void* plan, int cus,
+                         int republish, double seg_rest, int small_waves, int32_t* list,
+                         void* plan, void* big, int32_t* pool, int64_t pool_cap, int cus,
                          unsigned long long* stats, hipStream_t stream) {
   FastArgs fa;
+  fa.big = static_cast<BigInfo*>(big);
+  fa.pool = pool;
+  fa.pool_cap = pool_cap;
   fa.stats = stats;
+  fa.seg_rest = seg_rest;
   fa.s = s;
   fa.pos_bits = pos_bits;
   fa.t0_scale = t0_scale;
@@ -856,20 +1102,32 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
   fa.republish = republish;
   fa.list = list;
   fa.plan = static_cast<PlanState*>(plan);
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, stream, s, list, fa.plan, kLimS,
-                     kLimM);
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, stream, s, list, fa.plan, fa.big,
+                     pool_cap, t0_scale, kLimS, kLimM);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  for (int cls = 0; cls < kNumClasses; ++cls) {
-    fa.cls = cls;
-    const int waves = class_waves(cls, s.k_max);
-    e = segment_lanes(s.k_max) == 16 ? launch_class_w<16>(fa, waves, cus, stream)
-                                     : launch_class_w<64>(fa, waves, cus, stream);
-    if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(big_sum_kernel, dim3(cus * 4), dim3(kBigBlock), 0, stream, fa);
+  hipLaunchKernelGGL(big_probe_kernel, dim3(cus * 8), dim3(kBigBlock), 0, stream, fa);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // One persistent kernel per (size class, k class) that k_max can reach;
+  // an empty class exits at once.
+  for (int sc = 0; sc < kSizeClasses; ++sc) {
+    for (int kc = 0; kc < kKClasses; ++kc) {
+      const int lo = kc == 0 ? 1 : kclass_hi(kc - 1) + 1;
+      if (lo > s.k_max) break;
+      fa.cls = sc * kKClasses + kc;
+      fa.lds_k = s.k_max < kclass_hi(kc) ? s.k_max : kclass_hi(kc);
+      const int waves = class_waves(sc, fa.lds_k, small_waves);
+      e = segment_lanes(fa.lds_k) == 16 ? launch_class_w<16>(fa, waves, cus, stream)
+                                        : launch_class_w<64>(fa, waves, cus, stream);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
 
 size_t plan_state_bytes() { return sizeof(PlanState); }
+size_t big_info_bytes() { return sizeof(BigInfo); }
 
 }  // namespace gm

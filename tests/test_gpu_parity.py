@@ -92,7 +92,8 @@ def test_document_batch_k256(gm):
 @pytest.mark.parametrize("opt,val", [("pos_bits", 60), ("pos_bits", 40), ("map_load", 0),
                                      ("map_load", 2), ("map_load", 16), ("t0_scale_ppm", 1),
                                      ("t0_scale_ppm", 100_000), ("republish", 1),
-                                     ("republish", 64)])
+                                     ("republish", 64), ("seg_rest", 0),
+                                     ("seg_rest", 1000000)])
 def test_forced_internal_paths(gm, opt, val):
     """Debug knobs force packed-prefix contests (exact re-resolution), the
     wave-cooperative heavy path, the enlarge-and-repeat fallback and other
@@ -262,3 +263,42 @@ def test_long_vector_sampled(gm):
         print(f"long vector n+=1e6 k={k}", flush=True)
         _assert_same(_gpu_sketch(gm, idx, w, off, k, 1),
                      oracle.sketch(idx, w, off, k, 1, form=oracle.FORM_STREAM), f"k={k}")
+
+
+def _big_batch(seed=5):
+    rng = np.random.default_rng(seed)
+    rows_i, rows_w = [], []
+    for n in (50_000, 10, 33_000, 120_000, 500, 70_000, 40_000):
+        rows_i.append(W.distinct_sorted(rng, n, 1 << 24))
+        if n == 70_000:
+            ww = rng.lognormal(0.0, 2.0, size=n).astype(np.float32)
+        else:
+            ww = W.exp1_weights(rng, n)
+        rows_w.append(ww)
+    return W._pack(rows_i, rows_w)
+
+
+@pytest.mark.parametrize("k", [64, 1024])
+def test_big_vectors_candidate_lists(gm, k):
+    """Vectors above 32768 entries go through the grid-wide sum and probe
+    passes and are walked over their candidate lists."""
+    idx, w, off = _big_batch()
+    oracle.set_threads(8)
+    print(f"big vectors k={k}", flush=True)
+    _assert_same(_gpu_sketch(gm, idx, w, off, k, 21),
+                 oracle.sketch(idx, w, off, k, 21, form=oracle.FORM_STREAM), f"k={k}")
+
+
+@pytest.mark.parametrize("opt,val", [("t0_scale_ppm", 1), ("t0_scale_ppm", 300_000),
+                                     ("pos_bits", 56), ("map_load", 0)])
+def test_big_vectors_forced_paths(gm, opt, val):
+    """Empty or overflowing candidate lists fall back to the full vector;
+    forced contests re-resolve; none of it may change the sketch."""
+    idx, w, off = _big_batch(seed=6)
+    try:
+        gm.set_option(opt, val)
+        print(f"big vectors forced {opt}={val}", flush=True)
+        _assert_same(_gpu_sketch(gm, idx, w, off, 256, 22),
+                     oracle.sketch(idx, w, off, 256, 22, form=oracle.FORM_STREAM), f"{opt}={val}")
+    finally:
+        gm.reset_options()
