@@ -119,6 +119,14 @@ gm_status gm_sketch_batched(const int32_t *indices, const float *weights, const 
                             int32_t *out_idx, double *out_val, hipStream_t stream);
 
 /*
+ * gm_reserve -- create, on the current device, the workspace that FastGM
+ * calls on `stream` with up to nvec vectors need (planner lists, big-vector
+ * candidate pool), so that later calls allocate nothing.  Call it before
+ * capturing FastGM calls into a HIP graph on `stream`.  Synchronous.
+ */
+gm_status gm_reserve(int64_t nvec, hipStream_t stream);
+
+/*
  * gm_jaccard_est -- probability-Jaccard estimate of Sec. 1:
  *   out[p] = #{ j : a[p*k+j] == b[p*k+j] and a[p*k+j] >= 0 } / k
  * for npairs row-major pairs of Gumbel-ArgMax sketches (Theorem 1: unbiased
@@ -219,12 +227,90 @@ gm_status gm_set_option(gm_option opt, int64_t value);
 gm_status gm_get_stats(int64_t *host_counters, int32_t n, hipStream_t stream);
 gm_status gm_reset_stats(hipStream_t stream);
 
+/*
+ * gm_autotune -- pick the FastGM schedule options (GM_OPT_SMALL_WAVES,
+ * GM_OPT_SEG_REST, GM_OPT_MAP_LOAD, GM_OPT_REPUBLISH) for a batch like this
+ * one by timing it: coordinate descent over each option's grid, median of
+ * `reps` timed runs per point (HIP events on `stream`), then the best
+ * setting is applied process-wide.  Arguments as gm_sketch (k_per_vec and
+ * out_offsets null) or gm_sketch_batched (both non-null, k_max bounds k).
+ * With use_cache != 0 a JSON-lines cache ($GM_TUNE_CACHE, default
+ * ~/.cache/gm_tune.jsonl) keyed by (GPU arch, k_max, log2 nvec, log2 nnz,
+ * uniform or per-vector k) is consulted first and updated after tuning.
+ * The options change the work split, never the sketch.  Synchronises
+ * `stream`; runs the batch many times (outputs are overwritten).
+ */
+typedef struct {
+    int32_t small_waves, map_load, seg_rest, republish;
+    double ms;          /* median time of the chosen setting */
+    int32_t from_cache; /* 1 if taken from the cache without timing */
+} gm_tune_result;
+gm_status gm_autotune(const int32_t *indices, const float *weights, const int64_t *offsets,
+                      int64_t nvec, const int32_t *k_per_vec, const int64_t *out_offsets,
+                      int32_t k_max, uint64_t seed, int32_t *out_idx, double *out_val,
+                      int32_t reps, int32_t use_cache, gm_tune_result *result,
+                      hipStream_t stream);
+
+/*
+ * gm_serve_run -- continuous-batching request loop (sketch requests and
+ * probability-Jaccard queries against a device-resident sketch store).
+ * The trace `reqs` (nondecreasing arrival_us) is replayed open-loop against
+ * the host clock (config.realtime = 1) or with every request present at
+ * start (0).  Up to config.slots batches are in flight, one HIP stream each;
+ * a free slot admits pending requests in arrival order while the batch holds
+ * at most max_batch_requests requests and max_batch_entries sketch entries
+ * and the in-flight device bytes stay within device_budget_bytes; a partial
+ * batch waits for more requests until its oldest one has waited max_wait_us.
+ *   host_idx/host_w   host CSR entries of the sketch requests (request r
+ *                     sketches entries [a, b); b - a <= max_batch_entries)
+ *   store_idx         device [nstore * k] int32 sketch indices; a Jaccard
+ *                     request compares store rows a and b
+ *   out_sketch_idx/val  optional host [n_sketch * k] results, row i for the
+ *                     i-th sketch request of the trace
+ *   out_jaccard       host [nreq]: estimate of each Jaccard request
+ *   out_done_us       host [nreq]: completion time from trace start
+ * A request's sketch does not depend on what it was batched with.
+ * Synchronous; allocates and frees its own slots.
+ */
+enum { GM_REQ_SKETCH = 0, GM_REQ_JACCARD = 1 };
+typedef struct {
+    double arrival_us;
+    int32_t kind;
+    int32_t pad;
+    int64_t a, b;
+} gm_request;
+typedef struct {
+    int32_t k;
+    int32_t slots;
+    int32_t max_batch_requests;
+    int32_t realtime;
+    int64_t max_batch_entries;
+    int64_t device_budget_bytes;
+    double max_wait_us;
+    uint64_t seed;
+} gm_serve_config;
+typedef struct {
+    int64_t batches, sketch_requests, jaccard_requests, entries;
+    int64_t max_inflight_bytes, max_slots_busy, slots;
+    double wall_us;
+} gm_serve_stats;
+gm_status gm_serve_run(const gm_serve_config *cfg, const gm_request *reqs, int64_t nreq,
+                       const int32_t *host_idx, const float *host_w,
+                       const int32_t *store_idx, int64_t nstore,
+                       int32_t *out_sketch_idx, double *out_sketch_val,
+                       double *out_jaccard, double *out_done_us, gm_serve_stats *stats);
+
 /* gm_status_string -- static text for a status code. */
 const char *gm_status_string(gm_status status);
 
 /* gm_release -- free the library's per-device workspaces (call when no
  * stream still has library work queued). */
 void gm_release(void);
+
+/* gm_release_stream -- free the workspace that FastGM calls created for
+ * `stream` on the current device (synchronises the stream first); call it
+ * before destroying a stream that ran FastGM calls. */
+void gm_release_stream(hipStream_t stream);
 
 #ifdef __cplusplus
 }

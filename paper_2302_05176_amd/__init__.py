@@ -18,7 +18,7 @@ import ctypes
 from . import _native
 from ._native import GM_K_MAX, GMError  # noqa: F401
 
-__all__ = ["sketch", "sketch_batched", "jaccard_est", "jaccard_est_pairs", "wcard_est",
+__all__ = ["sketch", "sketch_batched", "reserve", "autotune", "jaccard_est", "jaccard_est_pairs", "wcard_est",
            "merge", "get_data_errors", "reset_data_errors", "set_option", "release",
            "GMError", "GM_K_MAX", "library_path"]
 
@@ -83,12 +83,14 @@ def sketch_batched(indices, weights, offsets, k_per_vec, out_offsets, k_max: int
     torch = _torch()
     L = _native.load()
     nvec = offsets.numel() - 1
-    total = int(out_offsets[-1].item()) if nvec > 0 else 0
     dev = offsets.device
-    if out_idx is None:
-        out_idx = torch.empty(total, dtype=torch.int32, device=dev)
-    if out_val is None:
-        out_val = torch.empty(total, dtype=torch.float64, device=dev)
+    if out_idx is None or out_val is None:
+        # sizing the outputs reads the device (a sync): pass them when capturing
+        total = int(out_offsets[-1].item()) if nvec > 0 else 0
+        if out_idx is None:
+            out_idx = torch.empty(total, dtype=torch.int32, device=dev)
+        if out_val is None:
+            out_val = torch.empty(total, dtype=torch.float64, device=dev)
     st = L.gm_sketch_batched(
         _dev(indices, torch.int32, "indices"), _dev(weights, torch.float32, "weights"),
         _dev(offsets, torch.int64, "offsets"), nvec, _dev(k_per_vec, torch.int32, "k_per_vec"),
@@ -154,6 +156,36 @@ def merge(idx, val, stream=None):
                     _stream(stream))
     _native.check(st, "gm_merge")
     return oi, ov
+
+
+def autotune(indices, weights, offsets, k_max: int, seed: int, k_per_vec=None, out_offsets=None,
+             out_idx=None, out_val=None, reps: int = 3, use_cache: bool = True, stream=None) -> dict:
+    """Time this batch under the FastGM schedule options, apply the fastest
+    (process-wide) and return it (gm_autotune; outputs are overwritten)."""
+    torch = _torch()
+    L = _native.load()
+    nvec = offsets.numel() - 1
+    dev = offsets.device
+    batched = k_per_vec is not None
+    if out_idx is None or out_val is None:
+        total = int(out_offsets[-1].item()) if batched else nvec * k_max
+        out_idx = torch.empty(total, dtype=torch.int32, device=dev)
+        out_val = torch.empty(total, dtype=torch.float64, device=dev)
+    res = _native.TuneResult()
+    st = L.gm_autotune(_dev(indices, torch.int32, "indices"), _dev(weights, torch.float32, "weights"),
+                       _dev(offsets, torch.int64, "offsets"), nvec,
+                       _dev(k_per_vec, torch.int32, "k_per_vec") if batched else None,
+                       _dev(out_offsets, torch.int64, "out_offsets") if batched else None,
+                       int(k_max), ctypes.c_uint64(seed), _dev(out_idx, torch.int32, "out_idx"),
+                       _dev(out_val, torch.float64, "out_val"), int(reps), int(bool(use_cache)),
+                       ctypes.byref(res), _stream(stream))
+    _native.check(st, "gm_autotune")
+    return {f: getattr(res, f) for f, _ in res._fields_}
+
+
+def reserve(nvec: int, stream=None) -> None:
+    """Create the FastGM workspace for `stream` up front (before graph capture)."""
+    _native.check(_native.load().gm_reserve(int(nvec), _stream(stream)), "gm_reserve")
 
 
 def get_data_errors(stream=None) -> int:

@@ -29,6 +29,12 @@ STATS = ["vectors", "iterations", "arrivals", "kept", "elements", "heavy", "heav
 _lib = None
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("small_waves", ctypes.c_int32), ("map_load", ctypes.c_int32),
+                ("seg_rest", ctypes.c_int32), ("republish", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
+
+
 class GMError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -63,13 +69,20 @@ def load() -> ctypes.CDLL:
     L.gm_set_option.argtypes = [ctypes.c_int, i64]
     L.gm_status_string.argtypes = [ctypes.c_int]
     L.gm_status_string.restype = ctypes.c_char_p
+    L.gm_reserve.argtypes = [i64, p]
+    L.gm_serve_run.argtypes = [p, p, i64, p, p, p, i64, p, p, p, p, p]
+    L.gm_autotune.argtypes = [p, p, p, i64, p, p, i32, u64, p, p, i32, i32,
+                              ctypes.POINTER(TuneResult), p]
     L.gm_get_stats.argtypes = [ctypes.POINTER(ctypes.c_int64), i32, p]
     L.gm_reset_stats.argtypes = [p]
+    L.gm_release_stream.argtypes = [p]
+    L.gm_release_stream.restype = None
     L.gm_release.argtypes = []
     L.gm_release.restype = None
     for name in ("gm_sketch", "gm_sketch_plain", "gm_sketch_batched", "gm_jaccard_est",
                  "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_get_data_errors",
-                 "gm_reset_data_errors", "gm_set_option", "gm_get_stats", "gm_reset_stats"):
+                 "gm_reset_data_errors", "gm_set_option", "gm_get_stats", "gm_reset_stats", "gm_reserve", "gm_autotune",
+                 "gm_serve_run"):
         getattr(L, name).restype = st
     _lib = L
     return L

@@ -202,6 +202,15 @@ gm_status gm_sketch_batched(const int32_t* indices, const float* weights, const 
                        seed, form, out_idx, out_val, stream);
 }
 
+gm_status gm_reserve(int64_t nvec, hipStream_t stream) {
+  if (nvec < 0 || nvec > 0x7FFFFFFF) return GM_ERR_INVALID_ARG;
+  DeviceState* st = nullptr;
+  gm_status s = device_state(&st);
+  if (s != GM_OK) return s;
+  PlanWorkspace* ws = nullptr;
+  return plan_workspace(st, stream, nvec > 0 ? nvec : 1, &ws);
+}
+
 gm_status gm_jaccard_est(const int32_t* idx_a, const int32_t* idx_b, int64_t npairs, int32_t k,
                          double* out, hipStream_t stream) {
   if (npairs < 0 || k < 1) return GM_ERR_INVALID_ARG;
@@ -326,6 +335,21 @@ const char* gm_status_string(gm_status status) {
     case GM_ERR_UNSUPPORTED: return "unsupported";
   }
   return "unknown status";
+}
+
+void gm_release_stream(hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceState& st = g_dev[dev];
+  auto it = st.plans.find(stream);
+  if (it == st.plans.end()) return;
+  (void)hipStreamSynchronize(stream);
+  if (it->second.list) (void)hipFree(it->second.list);
+  if (it->second.big) (void)hipFree(it->second.big);
+  if (it->second.plan) (void)hipFree(it->second.plan);
+  if (it->second.pool) (void)hipFree(it->second.pool);
+  st.plans.erase(it);
 }
 
 void gm_release(void) {

@@ -302,3 +302,53 @@ def test_big_vectors_forced_paths(gm, opt, val):
                      oracle.sketch(idx, w, off, 256, 22, form=oracle.FORM_STREAM), f"{opt}={val}")
     finally:
         gm.reset_options()
+
+
+def test_graph_capture_replays_match_eager(gm):
+    """A FastGM batched call (planner, big-vector passes, class kernels)
+    captured into a HIP graph gives the eager result on every replay, with
+    eager work and synchronisations between replays."""
+    idx, w, off, kk = W.uneven(nvec=400, seed=79, size_cap=40_000)
+    outoff = np.zeros(len(kk) + 1, np.int64)
+    np.cumsum(kk, out=outoff[1:])
+    t = lambda a: torch.from_numpy(a).to(DEV)
+    ti, tw, to, tk, too = t(idx), t(w), t(off), t(kk), t(outoff)
+    total = int(outoff[-1])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        gm.reserve(len(kk), stream=s)
+        ei, ev = gm.sketch_batched(ti, tw, to, tk, too, int(kk.max()), 13, stream=s)
+    s.synchronize()
+    ei, ev = ei.cpu().numpy(), ev.cpu().numpy()
+    gi = torch.empty(total, dtype=torch.int32, device=DEV)
+    gv = torch.empty(total, dtype=torch.float64, device=DEV)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        gm.sketch_batched(ti, tw, to, tk, too, int(kk.max()), 13, out_idx=gi, out_val=gv,
+                          stream=torch.cuda.current_stream())
+    for rep in range(4):
+        gi.fill_(-9)
+        gv.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(gi.cpu().numpy(), ei), f"replay {rep}"
+        assert np.array_equal(gv.cpu().numpy().view(np.uint64), ev.view(np.uint64)), f"replay {rep}"
+
+
+def test_autotune_keeps_results_and_caches(gm, tmp_path, monkeypatch):
+    """The autotuner only changes the schedule: the sketch after tuning equals
+    the oracle's, and a second call is answered from the cache."""
+    monkeypatch.setenv("GM_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    idx, w, off = W.mixed(seed=505, nvec=40, max_n=2000)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    try:
+        r1 = gm.autotune(t(idx), t(w), t(off), 128, 3, reps=1)
+        assert r1["from_cache"] == 0 and r1["ms"] > 0
+        r2 = gm.autotune(t(idx), t(w), t(off), 128, 3, reps=1)
+        assert r2["from_cache"] == 1
+        assert (r2["small_waves"], r2["seg_rest"]) == (r1["small_waves"], r1["seg_rest"])
+        _assert_same(_gpu_sketch(gm, idx, w, off, 128, 3),
+                     oracle.sketch(idx, w, off, 128, 3, form=oracle.FORM_STREAM), "tuned")
+    finally:
+        gm.reset_options()

@@ -1,0 +1,48 @@
+"""GPU: the continuous-batching serving loop.  Each sketch produced in the
+overlapped, batched run equals the same request sketched alone (and the
+oracle's); each Jaccard answer equals the oracle's estimate on the stored
+rows; every request completes after it arrives."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_serving_results_same_alone_and_in_the_mix():
+    import paper_2302_05176_amd as gm
+    from paper_2302_05176_amd import serve
+    k, nstore = 128, 3000
+    store = serve.build_store(nstore, k)
+    reqs, hi, hw = serve.make_trace(400, rate=20_000.0, nstore=nstore, size_mu=np.log(300.0),
+                                    size_sigma=1.0, size_cap=20_000)
+    res = serve.run(reqs, hi, hw, store, k, seed=7, slots=4, max_batch_requests=32,
+                    max_wait_us=100.0, want_sketches=True)
+    st = res["stats"]
+    assert st["sketch_requests"] + st["jaccard_requests"] == len(reqs)
+    assert st["batches"] > 1 and st["max_slots_busy"] >= 1
+    assert np.all(res["latency_us"] > 0)
+    sk = np.nonzero(reqs["kind"] == serve.SKETCH)[0]
+    # alone: every sketch request on its own
+    for row, r in enumerate(sk):
+        a, b = int(reqs["a"][r]), int(reqs["b"][r])
+        t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+        s1, y1 = gm.sketch(t(hi[a:b]), t(hw[a:b]), t(np.array([0, b - a], np.int64)), k, 7)
+        assert np.array_equal(s1.cpu().numpy()[0], res["sketch_idx"][row]), f"request {r}"
+        assert np.array_equal(y1.cpu().numpy()[0].view(np.uint64),
+                              res["sketch_val"][row].view(np.uint64)), f"request {r}"
+    # the oracle on a sample
+    for row in range(0, len(sk), 17):
+        r = sk[row]
+        a, b = int(reqs["a"][r]), int(reqs["b"][r])
+        os_, oy = oracle.sketch(hi[a:b], hw[a:b], np.array([0, b - a]), k, 7)
+        assert np.array_equal(os_[0], res["sketch_idx"][row])
+    st_h = store.cpu().numpy()
+    jq = np.nonzero(reqs["kind"] == serve.JACCARD)[0]
+    for r in jq:
+        want = oracle.jaccard(st_h[reqs["a"][r]], st_h[reqs["b"][r]])
+        assert res["jaccard"][r] == want, f"query {r}"
+    summ = serve.summarize(reqs, res)
+    assert summ["p99_us"] >= summ["p50_us"] > 0
