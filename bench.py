@@ -1,20 +1,28 @@
-"""Benchmark: batched Gumbel-Max sketching on one MI355X.
+"""Benchmark: Gumbel-Max sketching on one MI355X.
 
-One step = one FastGM-form sketch of the whole document-like batch already
-resident in HBM: 10,000 sparse vectors, n+ ~ lognormal(ln 500, 1) clipped to
-[10, 50000] (about 8.3 M entries), indices distinct in [0, 2^20), weights
-Exp(1) fp32, k = 256 registers per vector, FP64 keys.
+Default (the headline line): one step = one FastGM-form sketch of a
+document-like batch already resident in HBM -- 10,000 sparse vectors,
+n+ ~ lognormal(ln 500, 1) clipped to [10, 50000] (about 8.1 M entries),
+distinct indices in [0, 2^20), Exp(1) fp32 weights, k = 256 registers per
+vector, FP64 keys.  The JSON line reports registers/s (sum of k over the
+batch / step time) and vectors/s, the roofline of the dominant kernel
+(VALU-issue bound, durations from HIP events on its launch stream during
+the timed steps), the CPU oracle timed on the host cores, and -- measured
+after the timed steps -- the same batch at k = 1024 and the plain O(k n+)
+form at both k for the FastGM/plain ratio.
 
-Prints one JSON line: registers/s (sum of k over the batch / step time), plus
-vectors/s, the roofline of the FastGM kernel (VALU issue bound) measured with
-HIP events on the launch stream, and the CPU oracle timed on a bounded sample
-of the same batch.
+Other workloads (`--workload`), each printing its own line:
+  single  one vector, n+ = 1000, Uniform(0,1] weights, k = 128, both forms
+  stream  one vector, n+ = 1e7, half Uniform(0,1] / half Pareto(1.5), k = 1024 and 4096
+  uneven  uneven batch (Zipf n+, per-vector k in {64,256,1024,4096}, lognormal
+          weights), autotuned, replayed from a captured HIP graph
+  serve   continuous-batching serving loop, Poisson arrivals, k = 512, p50/p99
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -23,19 +31,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# VALU lane-operation peak of MI355X: 256 CUs x 64 lanes x 2.4 GHz (one
-# full-rate VALU instruction per lane per cycle).
-PEAK_VALU_OPS = 256 * 64 * 2.4e9
-# VALU issue slots of one FastGM arrival as compiled for gfx950 (hash of the
-# arrival draw and of the shuffle draw, -ln, the order-statistic fma, the key
-# multiply, the Fisher-Yates target); quarter-rate instructions (32-bit
-# integer multiplies, f64 reciprocal) count 4 slots.
-ARRIVAL_SLOTS = 180
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one
+# full-rate VALU lane-operation per lane per cycle.
+PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
+# Issue slots of one arrival of the draw specification as compiled for gfx950
+# (two splitmix64 hashes, the uniform, -ln, the c_z division, the fma, the key
+# multiply, the Fisher-Yates target): 106 VALU instructions, 15 of them
+# quarter-rate (32-bit integer multiplies, f64 reciprocal) counted 4 times.
+ARRIVAL_SLOTS = 151
+# One plain key (hash, uniform, -ln, multiply, compare): 88 VALU instructions,
+# 7 quarter-rate.
+PLAIN_KEY_SLOTS = 109
 HBM_PEAK = 8.0e12
+DOMINANT = "fastgm_class_kernel<1, 16>"
+SMALL_LIMIT = 2048   # vectors of at most this many entries go to the kernel above
 
 
 def harmonic(k: int) -> float:
     return sum(1.0 / m for m in range(1, k + 1))
+
+
+def source_digest() -> str:
+    csrc = os.path.join(ROOT, "paper_2302_05176_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    from the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_sha256") != source_digest():
+        return None
+    return ent.get("bytes_per_launch")
 
 
 def parse():
@@ -43,107 +81,145 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["batch", "single", "stream", "uneven", "serve"],
+                    default="batch")
     ap.add_argument("--form", choices=["fastgm", "plain"], default="fastgm")
     ap.add_argument("--k", type=int, default=256)
     ap.add_argument("--nvec", type=int, default=10000)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2000,
-                    help="vectors of the batch the CPU oracle sketches")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=2.0,
+                    help="wall seconds of oracle work for the CPU baseline")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run one device copy of this many bytes (counter calibration)")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sketch "
-              "batch is independent per vector, so N GPUs would each run this line on "
-              "their own share.", file=sys.stderr)
-        sys.exit(2)
+def timed_steps(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        starts[s].record(stream)
+        fn()
+        ends[s].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = [a.elapsed_time(b) for a, b in zip(starts, ends)]
+    return wall * 1e3 / steps, sum(ev) / len(ev)
+
+
+def cpu_baseline(idx, w, off, k, seed, seconds, form):
+    import oracle
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    ncores = max(1, min(ncores, 16))
+    oracle.set_threads(ncores)
+    nvec = len(off) - 1
+    f = oracle.FORM_STREAM if form == "fastgm" else oracle.FORM_PLAIN
+    sub = off if form == "fastgm" else off[: min(nvec, 200) + 1]
+    nv = len(sub) - 1
+    done, t0 = 0, time.perf_counter()
+    while True:
+        oracle.sketch(idx, w, sub, k, seed + done, form=f)
+        done += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            break
+    what = ("Algorithm 2 (Stream-FastGM)" if form == "fastgm" else "plain O(k n+)")
+    return {"value": done * nv * k / dt, "unit": "registers/s", "cores": ncores, "kind": "oracle",
+            "sample": f"{what} over the first {nv} vectors of the batch, {done} pass(es) with "
+                      f"different seeds, {dt:.1f} s wall on {ncores} threads"}
+
+
+def bench_batch(args):
     import numpy as np
     import torch
 
     import paper_2302_05176_amd as gm
-    from paper_2302_05176_amd import build as gmbuild
     from paper_2302_05176_amd import workloads as W
 
-    if not os.path.exists(gmbuild.LIB):
-        gmbuild.build(force=True)
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     idx, w, off = W.batch(nvec=args.nvec, seed=1002)
     nnz = int(off[-1])
+    nplus = np.diff(off)
     k = args.k
-    ti = torch.from_numpy(idx).to(dev)
-    tw = torch.from_numpy(w).to(dev)
-    to = torch.from_numpy(off).to(dev)
+    ti, tw, to = (torch.from_numpy(a).to(dev) for a in (idx, w, off))
     out_i = torch.empty((args.nvec, k), dtype=torch.int32, device=dev)
     out_v = torch.empty((args.nvec, k), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
-
+    gm.reset_options()
+    if args.copy_bytes:
+        a = torch.empty(args.copy_bytes // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+    step = lambda kk=k, form=args.form, oi=out_i, ov=out_v: gm.sketch(
+        ti, tw, to, kk, args.seed, form=form, out_idx=oi, out_val=ov)
+    gm.set_option("timing", 1)
     for _ in range(args.warmup):
-        gm.sketch(ti, tw, to, k, args.seed, form=args.form, out_idx=out_i, out_val=out_v)
+        step()
     torch.cuda.synchronize()
-
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        starts[s].record(stream)
-        gm.sketch(ti, tw, to, k, args.seed, form=args.form, out_idx=out_i, out_val=out_v)
-        ends[s].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in zip(starts, ends)]
-    ms_step = wall * 1e3 / args.steps
-    avg_kern_s = sum(kern_ms) / len(kern_ms) / 1e3
-
+    gm.reset_timing()
+    ms_step, ev_ms = timed_steps(step, args.steps, 0, stream)
+    kt = gm.get_timing()
+    gm.set_option("timing", 0)
     regs = args.nvec * k
     value = regs / (ms_step / 1e3)
-    nplus = np.diff(off)
     if args.form == "fastgm":
-        # expected arrivals of an exact pruned run: k H_k + n+ per vector (Sec. 2.5)
-        units = float(args.nvec * k * harmonic(k) + nnz)
+        kern = DOMINANT
+        small = nplus <= SMALL_LIMIT
+        units = float(small.sum() * k * harmonic(k) + nplus[small].sum())
+        slots = ARRIVAL_SLOTS
+        unit_name = "arrivals (k H_k + n+ per vector, vectors of the kernel's class)"
+        vec_bytes = 8.0 * nplus[small].sum() + 8.0 * (small.sum() + 1) + 12.0 * small.sum() * k
     else:
+        kern = "plain_kernel"
         units = float(k) * nnz
-    ops = units * ARRIVAL_SLOTS
-    achieved = ops / avg_kern_s
-    bytes_alg = 8.0 * nnz + 8.0 * (args.nvec + 1) + 12.0 * regs
+        slots = PLAIN_KEY_SLOTS
+        unit_name = "keys (k n+)"
+        vec_bytes = 8.0 * nnz + 8.0 * (args.nvec + 1) + 12.0 * regs
+    tot_ms, launches = kt.get(kern, (0.0, 0))
+    kern_s = tot_ms / launches / 1e3 if launches else ev_ms / 1e3
+    achieved = units * slots / kern_s
+    traffic = committed_traffic(kern, f"batch_k{k}_{args.form}")
     roofline = {
         "bound": "alu",
         "achieved": achieved / 1e12,
         "peak": PEAK_VALU_OPS / 1e12,
-        "unit": "TOPS (VALU lane-ops/s)",
+        "unit": "TOPS (VALU lane-ops/s: algorithmic units x issue slots per unit)",
         "frac": achieved / PEAK_VALU_OPS,
-        "traffic": None,
-        "kernel": "fastgm_kernel" if args.form == "fastgm" else "plain_kernel",
-        "kernel_ms": avg_kern_s * 1e3,
+        "traffic": traffic,
+        "kernel": kern,
+        "kernel_ms": kern_s * 1e3,
         "algorithmic_units": units,
-        "unit_name": "arrivals" if args.form == "fastgm" else "keys",
-        "slots_per_unit": ARRIVAL_SLOTS,
-        "hbm_frac": bytes_alg / avg_kern_s / HBM_PEAK,
+        "unit_name": unit_name,
+        "slots_per_unit": slots,
+        "hbm_algorithmic_frac": vec_bytes / kern_s / HBM_PEAK,
+        "kernels_ms_per_step": {n: t / c for n, (t, c) in kt.items() if c},
     }
-
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-        ncores = min(ncores, 16)
-        oracle.set_threads(ncores)
-        m = min(args.cpu_sample, args.nvec)
-        so = off[: m + 1]
-        c0 = time.perf_counter()
-        oracle.sketch(idx, w, so, k, args.seed,
-                      form=oracle.FORM_STREAM if args.form == "fastgm" else oracle.FORM_PLAIN)
-        cdt = time.perf_counter() - c0
-        cpu = {"value": m * k / cdt, "unit": "registers/s", "cores": ncores, "kind": "oracle",
-               "sample": f"first {m} of the {args.nvec} vectors, "
-                         f"{'Algorithm 2 (Stream-FastGM)' if args.form == 'fastgm' else 'plain O(k n+)'}"
-                         f", {cdt:.2f} s"}
-
+        cpu = cpu_baseline(idx, w, off, k, args.seed, args.cpu_seconds, args.form)
+    extras = {}
+    if not args.no_extras and args.form == "fastgm":
+        # same batch at k = 1024 and the plain form, a few steps each
+        o2i = torch.empty((args.nvec, 1024), dtype=torch.int32, device=dev)
+        o2v = torch.empty((args.nvec, 1024), dtype=torch.float64, device=dev)
+        f1024, _ = timed_steps(lambda: step(1024, "fastgm", o2i, o2v), 5, 1, stream)
+        p256, _ = timed_steps(lambda: step(k, "plain", out_i, out_v), 3, 1, stream)
+        p1024, _ = timed_steps(lambda: step(1024, "plain", o2i, o2v), 2, 1, stream)
+        extras = {"fastgm_k1024_ms": f1024, "fastgm_k1024_registers_per_s": args.nvec * 1024 / (f1024 / 1e3),
+                  "plain_k256_ms": p256, "plain_k1024_ms": p1024,
+                  f"speedup_vs_plain_k{k}": p256 / ms_step, "speedup_vs_plain_k1024": p1024 / f1024}
     line = {
-        "metric": f"Gumbel-Max registers/sec (k={k})",
+        "metric": "Gumbel-Max registers/sec (FastGM form, k=256 document batch)" if k == 256
+        else f"Gumbel-Max registers/sec (k={k} document batch)",
         "value": value,
         "unit": "registers/s",
         "n_gpus": 1,
@@ -156,15 +232,150 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "vectors_per_s": args.nvec / (ms_step / 1e3),
-        "config": {"workload": f"document batch: {args.nvec} sparse vectors, n+ ~ "
-                               f"lognormal(ln 500, 1) in [10, 50000] (nnz={nnz}), Exp(1) "
-                               f"fp32 weights, k={k}, {args.form} form",
+        "config": {"workload": f"document batch: {args.nvec} sparse vectors, n+ ~ lognormal(ln 500, 1) "
+                               f"clipped to [10, 50000] (nnz={nnz}), indices in [0, 2^20), Exp(1) fp32 "
+                               f"weights, k={k}, {args.form} form",
                    "form": args.form, "k": k, "nvec": args.nvec, "nnz": nnz,
                    "mean_nplus": float(nplus.mean())},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_single(args):
+    import numpy as np
+    import torch
+
+    import paper_2302_05176_amd as gm
+    from paper_2302_05176_amd import workloads as W
+    dev = torch.device("cuda:0")
+    idx, w, off = W.single(nplus=1000)
+    ti, tw, to = (torch.from_numpy(a).to(dev) for a in (idx, w, off))
+    stream = torch.cuda.current_stream()
+    res = {}
+    for form in ("fastgm", "plain"):
+        ms, ev = timed_steps(lambda: gm.sketch(ti, tw, to, 128, args.seed, form=form),
+                             args.steps, args.warmup, stream)
+        res[form] = {"ms_per_sketch": ms, "event_ms": ev}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.set_threads(1)
+        for form, f in (("fastgm", oracle.FORM_STREAM), ("plain", oracle.FORM_PLAIN)):
+            t0 = time.perf_counter()
+            n = 0
+            while time.perf_counter() - t0 < 1.0:
+                oracle.sketch(idx, w, off, 128, args.seed + n, form=f)
+                n += 1
+            res[form]["cpu_oracle_ms_1thread"] = (time.perf_counter() - t0) * 1e3 / n
+    print(json.dumps({"workload": "single vector n+=1000, Uniform(0,1] weights, k=128",
+                      "results": res}), flush=True)
+
+
+def bench_stream(args):
+    import torch
+
+    import paper_2302_05176_amd as gm
+    from paper_2302_05176_amd import workloads as W
+    dev = torch.device("cuda:0")
+    idx, w, off = W.stream(nplus=10_000_000)
+    ti, tw, to = (torch.from_numpy(a).to(dev) for a in (idx, w, off))
+    stream = torch.cuda.current_stream()
+    S = float(w.astype("float64").sum())
+    out = {}
+    for k in (1024, 4096):
+        ms, _ = timed_steps(lambda: gm.sketch(ti, tw, to, k, args.seed), args.steps, args.warmup,
+                            stream)
+        ests = []
+        for seed in range(1, 101):
+            _, y = gm.sketch(ti, tw, to, k, seed)
+            ests.append(float(gm.wcard_est(y).item()))
+        import numpy as np
+        r = np.array(ests) / S
+        out[f"k{k}"] = {"ms_per_sketch": ms, "registers_per_s": k / (ms / 1e3),
+                        "entries_per_s": 1e7 / (ms / 1e3),
+                        "wcard_mean_ratio": float(r.mean()), "wcard_rel_var_x_(k-2)": float(r.var(ddof=1) * (k - 2))}
+    pms, _ = timed_steps(lambda: gm.sketch(ti, tw, to, 1024, args.seed, form="plain"), 1, 0, stream)
+    out["plain_k1024_ms"] = pms
+    out["speedup_vs_plain_k1024"] = pms / out["k1024"]["ms_per_sketch"]
+    print(json.dumps({"workload": "one stream vector n+=1e7, half Uniform(0,1], half 1+Pareto(1.5)",
+                      "results": out}), flush=True)
+
+
+def bench_uneven(args):
+    import numpy as np
+    import torch
+
+    import paper_2302_05176_amd as gm
+    from paper_2302_05176_amd import workloads as W
+    dev = torch.device("cuda:0")
+    nvec = args.nvec if args.nvec != 10000 else 100_000
+    t0 = time.perf_counter()
+    idx, w, off, kk = W.uneven(nvec=nvec)
+    gen_s = time.perf_counter() - t0
+    outoff = np.zeros(nvec + 1, np.int64)
+    np.cumsum(kk, out=outoff[1:])
+    t = lambda a: torch.from_numpy(a).to(dev)
+    ti, tw, to, tk, too = t(idx), t(w), t(off), t(kk), t(outoff)
+    total = int(outoff[-1])
+    oi = torch.empty(total, dtype=torch.int32, device=dev)
+    ov = torch.empty(total, dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        gm.reserve(nvec, stream=s)
+        tuned = gm.autotune(ti, tw, to, 4096, args.seed, k_per_vec=tk, out_offsets=too,
+                            out_idx=oi, out_val=ov, reps=1, stream=s)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        gm.sketch_batched(ti, tw, to, tk, too, 4096, args.seed, out_idx=oi, out_val=ov,
+                          stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    ms, _ = timed_steps(lambda: g.replay(), max(2, args.steps // 4), 1, torch.cuda.current_stream())
+    gm.reset_options()
+    print(json.dumps({"workload": f"uneven batch: {nvec} vectors, Zipf(1.2) n+ on [10, 1e5] "
+                                  f"(nnz={int(off[-1])}), k from {{64,256,1024,4096}}, lognormal(0,2) weights",
+                      "ms_per_batch": ms, "registers_per_s": total / (ms / 1e3),
+                      "vectors_per_s": nvec / (ms / 1e3), "entries_per_s": int(off[-1]) / (ms / 1e3),
+                      "autotuned": tuned, "graph": True, "input_gen_s": gen_s}), flush=True)
+
+
+def bench_serve(args):
+    import numpy as np
+    import torch
+
+    from paper_2302_05176_amd import serve
+    nstore = 1_000_000
+    k = 512
+    t0 = time.perf_counter()
+    store = serve.build_store(nstore, k)
+    build_s = time.perf_counter() - t0
+    reqs, hi, hw = serve.make_trace(20_000, rate=20_000.0, nstore=nstore)
+    res = serve.run(reqs, hi, hw, store, k, seed=args.seed, slots=4, max_batch_requests=256,
+                    max_wait_us=200.0, device_budget_bytes=4 << 30)
+    summ = serve.summarize(reqs, res)
+    print(json.dumps({"workload": "serving: Poisson 20,000 req/s, 1 sketch (k=512, n+ ~ "
+                                  "lognormal(ln 2000, 1.5)) per 4 Jaccard queries on 1e6 stored sketches",
+                      "requests": len(reqs), "summary": summ, "stats": res["stats"],
+                      "store_build_s": build_s}), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}); vectors are "
+              "independent, so N GPUs would each sketch their own share of the batch.",
+              file=sys.stderr)
+        sys.exit(2)
+    from paper_2302_05176_amd import build as gmbuild
+    if not os.path.exists(gmbuild.LIB):
+        gmbuild.build(force=True)
+    import torch
+    torch.cuda.set_device(0)
+    {"batch": bench_batch, "single": bench_single, "stream": bench_stream,
+     "uneven": bench_uneven, "serve": bench_serve}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -198,6 +198,8 @@ gm_status gm_reset_data_errors(hipStream_t stream);
  *                        continuing element does).
  *   GM_OPT_SMALL_WAVES   [0] waves that share one small vector (0: chosen
  *                        from k; else 1, 2, 4 or 8).
+ *   GM_OPT_TIMING        [0] 1 brackets every sketch-kernel launch with HIP
+ *                        events on its stream (read with gm_get_timing).
  *   GM_OPT_STATS         [0] 1 makes FastGM calls accumulate work counters
  *                        (read them with gm_get_stats); costs a few atomics
  *                        per vector.
@@ -210,7 +212,8 @@ typedef enum {
     GM_OPT_REPUBLISH = 3,
     GM_OPT_STATS = 4,
     GM_OPT_SEG_REST = 5,
-    GM_OPT_SMALL_WAVES = 6
+    GM_OPT_SMALL_WAVES = 6,
+    GM_OPT_TIMING = 7
 } gm_option;
 gm_status gm_set_option(gm_option opt, int64_t value);
 
@@ -226,6 +229,15 @@ gm_status gm_set_option(gm_option opt, int64_t value);
  */
 gm_status gm_get_stats(int64_t *host_counters, int32_t n, hipStream_t stream);
 gm_status gm_reset_stats(hipStream_t stream);
+
+/*
+ * gm_get_timing -- waits for the timed launches made while GM_OPT_TIMING
+ * was 1, then copies up to n entries: kernel name (as the profiler names the
+ * instance), total milliseconds and launch count.  Returns the number of
+ * entries copied.  gm_reset_timing clears the totals.
+ */
+int32_t gm_get_timing(int32_t n, char (*names)[64], double *total_ms, int64_t *launches);
+void gm_reset_timing(void);
 
 /*
  * gm_autotune -- pick the FastGM schedule options (GM_OPT_SMALL_WAVES,

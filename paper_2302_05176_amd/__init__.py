@@ -216,6 +216,22 @@ def get_stats(stream=None) -> dict:
     return dict(zip(_native.STATS, list(buf)))
 
 
+def get_timing() -> dict:
+    """Per-kernel HIP-event totals of launches made while set_option("timing", 1):
+    {kernel name: (total ms, launches)}."""
+    L = _native.load()
+    n = 64
+    names = (ctypes.c_char * 64 * n)()
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    m = L.gm_get_timing(n, names, ms, cnt)
+    return {bytes(names[i]).split(b"\0")[0].decode(): (ms[i], cnt[i]) for i in range(max(m, 0))}
+
+
+def reset_timing() -> None:
+    _native.load().gm_reset_timing()
+
+
 def reset_stats(stream=None) -> None:
     _native.check(_native.load().gm_reset_stats(_stream(stream)), "gm_reset_stats")
 
@@ -223,7 +239,7 @@ def reset_stats(stream=None) -> None:
 def reset_options() -> None:
     for name, v in (("pos_bits", 24), ("t0_scale_ppm", 1_000_000), ("map_load", 10),
                     ("republish", 4), ("stats", 0), ("seg_rest", 16),
-                    ("small_waves", 0)):
+                    ("small_waves", 0), ("timing", 0)):
         set_option(name, v)
 
 

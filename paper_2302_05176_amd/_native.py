@@ -22,7 +22,7 @@ GM_FORM_PLAIN = 1
 GM_K_MAX = 4096
 
 OPTIONS = {"pos_bits": 0, "t0_scale_ppm": 1, "map_load": 2, "republish": 3, "stats": 4,
-           "seg_rest": 5, "small_waves": 6}
+           "seg_rest": 5, "small_waves": 6, "timing": 7}
 STATS = ["vectors", "iterations", "arrivals", "kept", "elements", "heavy", "heavy_batches",
          "passes", "resolves"]
 
@@ -75,6 +75,10 @@ def load() -> ctypes.CDLL:
                               ctypes.POINTER(TuneResult), p]
     L.gm_get_stats.argtypes = [ctypes.POINTER(ctypes.c_int64), i32, p]
     L.gm_reset_stats.argtypes = [p]
+    L.gm_get_timing.argtypes = [i32, p, p, p]
+    L.gm_get_timing.restype = i32
+    L.gm_reset_timing.argtypes = []
+    L.gm_reset_timing.restype = None
     L.gm_release_stream.argtypes = [p]
     L.gm_release_stream.restype = None
     L.gm_release.argtypes = []

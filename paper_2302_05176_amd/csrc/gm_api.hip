@@ -17,6 +17,9 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
                          void* plan, void* big, int32_t* pool, int64_t pool_cap, int cus,
                          unsigned long long* stats, hipStream_t stream);
 size_t plan_state_bytes();
+void timing_enable(bool on);
+int timing_collect(int n, char (*names)[64], double* ms, long long* launches);
+void timing_reset();
 size_t big_info_bytes();
 hipError_t launch_jaccard(const int32_t* a, const int32_t* b, int64_t npairs, int32_t k,
                           double* out, hipStream_t stream);
@@ -291,6 +294,13 @@ gm_status gm_set_option(gm_option opt, int64_t value) {
         return GM_ERR_INVALID_ARG;
       g_small_waves = static_cast<int>(value);
       return GM_OK;
+    case GM_OPT_TIMING:
+      if (value != 0 && value != 1) return GM_ERR_INVALID_ARG;
+      {
+        std::lock_guard<std::mutex> lock(g_mu);
+        gm::timing_enable(value != 0);
+      }
+      return GM_OK;
     case GM_OPT_STATS:
       if (value != 0 && value != 1) return GM_ERR_INVALID_ARG;
       g_stats = value != 0;
@@ -315,6 +325,20 @@ gm_status gm_get_stats(int64_t* host_counters, int32_t n, hipStream_t stream) {
   if (e != hipSuccess) return from_hip(e);
   for (int i = 0; i < n; ++i) host_counters[i] = static_cast<int64_t>(v[i]);
   return GM_OK;
+}
+
+int32_t gm_get_timing(int32_t n, char (*names)[64], double* total_ms, int64_t* launches) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (n < 0) return -1;
+  std::vector<long long> l(static_cast<size_t>(n > 0 ? n : 1));
+  const int m = gm::timing_collect(n, names, total_ms, l.data());
+  for (int i = 0; i < m; ++i) launches[i] = l[i];
+  return m;
+}
+
+void gm_reset_timing(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  gm::timing_reset();
 }
 
 gm_status gm_reset_stats(hipStream_t stream) {

@@ -48,7 +48,10 @@
 //  * Exact indices on contest: walk again with the exact final y* and, for
 //    every arrival whose key equals its register's final key, atomic-min the
 //    element index into the register.
+#include <cstdio>
+#include <string>
 #include <utility>
+#include <vector>
 
 #include "gm_common.h"
 
@@ -1038,6 +1041,103 @@ int class_waves(int sc, int k_max, int small_waves) {
   return w;
 }
 
+// ---------------------------------------------------------------------------
+// Optional per-kernel timing: HIP events recorded around each FastGM launch on
+// its own stream, summed per kernel instance by gm_get_timing.
+struct TimedLaunch {
+  int id;
+  hipEvent_t a, b;
+};
+
+struct TimingState {
+  bool on = false;
+  std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> free_events;
+  std::vector<std::string> names;
+  std::vector<double> total_ms;
+  std::vector<long long> launches;
+};
+
+TimingState& timing() {
+  static TimingState t;
+  return t;
+}
+
+void timing_enable(bool on) { timing().on = on; }
+
+static int timing_id(const std::string& name) {
+  TimingState& t = timing();
+  for (size_t i = 0; i < t.names.size(); ++i)
+    if (t.names[i] == name) return static_cast<int>(i);
+  t.names.push_back(name);
+  t.total_ms.push_back(0.0);
+  t.launches.push_back(0);
+  return static_cast<int>(t.names.size()) - 1;
+}
+
+static hipEvent_t timing_event() {
+  TimingState& t = timing();
+  if (!t.free_events.empty()) {
+    hipEvent_t e = t.free_events.back();
+    t.free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Bracket one launch (returns -1 when timing is off).
+static int timing_begin(const std::string& name, hipStream_t stream, hipEvent_t* a) {
+  if (!timing().on) return -1;
+  *a = timing_event();
+  (void)hipEventRecord(*a, stream);
+  return timing_id(name);
+}
+
+static void timing_end(int id, hipEvent_t a, hipStream_t stream) {
+  if (id < 0) return;
+  hipEvent_t b = timing_event();
+  (void)hipEventRecord(b, stream);
+  timing().pending.push_back(TimedLaunch{id, a, b});
+}
+
+// Sum the finished launches; copy up to n (name, total ms, launches).
+int timing_collect(int n, char (*names)[64], double* ms, long long* launches) {
+  TimingState& t = timing();
+  for (TimedLaunch& l : t.pending) {
+    (void)hipEventSynchronize(l.b);
+    float m = 0.0f;
+    if (hipEventElapsedTime(&m, l.a, l.b) == hipSuccess) {
+      t.total_ms[l.id] += m;
+      t.launches[l.id] += 1;
+    }
+    t.free_events.push_back(l.a);
+    t.free_events.push_back(l.b);
+  }
+  t.pending.clear();
+  const int m = static_cast<int>(t.names.size()) < n ? static_cast<int>(t.names.size()) : n;
+  for (int i = 0; i < m; ++i) {
+    std::snprintf(names[i], 64, "%s", t.names[i].c_str());
+    ms[i] = t.total_ms[i];
+    launches[i] = t.launches[i];
+  }
+  return m;
+}
+
+void timing_reset() {
+  TimingState& t = timing();
+  (void)timing_collect(0, nullptr, nullptr, nullptr);
+  t.names.clear();
+  t.total_ms.clear();
+  t.launches.clear();
+}
+
+int timing_begin_plain(hipStream_t stream, hipEvent_t* a) {
+  return timing_begin("plain_kernel", stream, a);
+}
+void timing_end_plain(int id, hipEvent_t a, hipStream_t stream) { timing_end(id, a, stream); }
+
 struct OccKey {
   const void* fn;
   size_t lds;
@@ -1065,8 +1165,13 @@ static hipError_t launch_class(const FastArgs& fa, int cus, hipStream_t stream) 
   }
   int64_t grid = static_cast<int64_t>(cus) * per_cu;
   if (grid > fa.s.nvec) grid = fa.s.nvec;
+  hipEvent_t ta = nullptr;
+  const int tid = timing_begin("fastgm_class_kernel<" + std::to_string(W) + ", " +
+                                   std::to_string(G) + ">",
+                               stream, &ta);
   hipLaunchKernelGGL((fastgm_class_kernel<W, G>), dim3(static_cast<unsigned>(grid)), dim3(W * kWave),
                      lds, stream, fa);
+  timing_end(tid, ta, stream);
   return hipGetLastError();
 }
 
@@ -1102,12 +1207,19 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
   fa.republish = republish;
   fa.list = list;
   fa.plan = static_cast<PlanState*>(plan);
+  hipEvent_t ta = nullptr;
+  int tid = timing_begin("plan_kernel", stream, &ta);
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, stream, s, list, fa.plan, fa.big,
                      pool_cap, t0_scale, kLimS, kLimM);
+  timing_end(tid, ta, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  tid = timing_begin("big_sum_kernel", stream, &ta);
   hipLaunchKernelGGL(big_sum_kernel, dim3(cus * 4), dim3(kBigBlock), 0, stream, fa);
+  timing_end(tid, ta, stream);
+  tid = timing_begin("big_probe_kernel", stream, &ta);
   hipLaunchKernelGGL(big_probe_kernel, dim3(cus * 8), dim3(kBigBlock), 0, stream, fa);
+  timing_end(tid, ta, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // One persistent kernel per (size class, k class) that k_max can reach;

@@ -95,11 +95,17 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(SketchArgs p) {
   }
 }
 
+int timing_begin_plain(hipStream_t stream, hipEvent_t* a);
+void timing_end_plain(int id, hipEvent_t a, hipStream_t stream);
+
 hipError_t launch_plain(const SketchArgs& p, hipStream_t stream) {
   const int tiles = (p.k_max + kPlainBlock - 1) / kPlainBlock;
   const int64_t gx = p.nvec < (1 << 22) ? p.nvec : (1 << 22);
   dim3 grid(static_cast<unsigned>(gx), static_cast<unsigned>(tiles));
+  hipEvent_t ta = nullptr;
+  const int tid = timing_begin_plain(stream, &ta);
   hipLaunchKernelGGL(plain_kernel, grid, dim3(kPlainBlock), 0, stream, p);
+  timing_end_plain(tid, ta, stream);
   return hipGetLastError();
 }
 
