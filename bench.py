@@ -55,18 +55,22 @@ def source_digest() -> str:
     csrc = os.path.join(ROOT, "paper_2302_05176_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
+        if not name.endswith((".hip", ".h", ".cpp")):
+            continue
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
     return h.hexdigest()
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.document_batch.txt")
+
+
 def committed_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed counter summary, if it was taken
     from the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
-        with open(path) as f:
+        with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
@@ -74,6 +78,57 @@ def committed_traffic(kernel: str, workload: str):
     if not ent or ent.get("source_sha256") != source_digest():
         return None
     return ent.get("bytes_per_launch")
+
+
+def _counter_rows(d):
+    import csv
+    rows = []
+    for dirpath, _, files in os.walk(d):
+        for fn in files:
+            if fn.endswith("counter_collection.csv"):
+                with open(os.path.join(dirpath, fn)) as f:
+                    rows += list(csv.DictReader(f))
+    return rows
+
+
+def summarize_pmc(args):
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, both with --copy-bytes) into HBM bytes per launch of every
+    kernel, each counter scaled so that the calibration copy reads/writes
+    exactly its size."""
+    fetch_dir, write_dir = args.summarize_pmc
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = {}
+        for r in _counter_rows(d):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"]
+            per.setdefault(name, []).append(float(r["Counter_Value"]) * 1024.0)
+        calib = [v for n, vs in per.items() if "elementwise" in n and "Mul" in n for v in vs]
+        if not calib:
+            raise SystemExit(f"no calibration copy dispatch found for {counter} in {d}")
+        factor = args.copy_bytes / (sum(calib) / len(calib))
+        for name, vs in per.items():
+            short = name.split("(")[0].replace("void ", "").replace("gm::", "")
+            e = out.setdefault(short, {"launches": len(vs)})
+            e[counter.lower() + "_raw_bytes"] = sum(vs) / len(vs)
+            e[counter.lower() + "_factor"] = factor
+            e[counter.lower() + "_bytes"] = sum(vs) / len(vs) * factor
+    for e in out.values():
+        e["bytes_per_launch"] = e.get("fetch_size_bytes", 0.0) + e.get("write_size_bytes", 0.0)
+        e["source_sha256"] = source_digest()
+    workload = f"batch_k{args.k}_{args.form}"
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        rec = {}
+    rec[workload] = {n: e for n, e in out.items() if "elementwise" not in n}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps(rec[workload], indent=1))
 
 
 def parse():
@@ -89,10 +144,12 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=2.0,
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall seconds of oracle work for the CPU baseline")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device copy of this many bytes (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write HBM bytes per launch from two rocprofv3 --pmc output folders")
     return ap.parse_args()
 
 
@@ -155,10 +212,13 @@ def bench_batch(args):
     stream = torch.cuda.current_stream()
     gm.reset_options()
     if args.copy_bytes:
-        a = torch.empty(args.copy_bytes // 4, dtype=torch.float32, device=dev)
+        # counter calibration: one elementwise kernel that reads and writes
+        # copy_bytes each
+        a = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
+        del a, b
     step = lambda kk=k, form=args.form, oi=out_i, ov=out_v: gm.sketch(
         ti, tw, to, kk, args.seed, form=form, out_idx=oi, out_val=ov)
     gm.set_option("timing", 1)
@@ -364,6 +424,9 @@ def bench_serve(args):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(args)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU (asked for --gpus {args.gpus}); vectors are "
               "independent, so N GPUs would each sketch their own share of the batch.",

@@ -14,9 +14,11 @@ namespace gm {
 hipError_t launch_plain(const SketchArgs& p, hipStream_t stream);
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
                          int republish, double seg_rest, int small_waves, int32_t* list,
-                         void* plan, void* big, int32_t* pool, int64_t pool_cap, int cus,
+                         void* plan, void* big, int32_t* pool, int64_t pool_cap,
+                         int32_t* heavy, int64_t heavy_waves, int cus,
                          unsigned long long* stats, hipStream_t stream);
 size_t plan_state_bytes();
+int64_t heavy_list_entries();
 void timing_enable(bool on);
 int timing_collect(int n, char (*names)[64], double* ms, long long* launches);
 void timing_reset();
@@ -49,7 +51,12 @@ struct PlanWorkspace {
   int64_t cap = 0;
   void* plan = nullptr;
   int32_t* pool = nullptr;
+  int32_t* heavy = nullptr;   // per-wave heavy-element lists of the FastGM walk
+  int64_t heavy_waves = 0;
 };
+
+// Resident waves per CU the heavy lists are sized for (2048 threads / 64).
+constexpr int kMaxWavesPerCu = 32;
 
 constexpr int kStatSlots = 16;
 
@@ -122,6 +129,11 @@ gm_status plan_workspace(DeviceState* st, hipStream_t stream, int64_t nvec, Plan
     e = hipMalloc(&q, sizeof(int32_t) * static_cast<size_t>(kPoolCap));
     if (e != hipSuccess) return from_hip(e);
     ws.pool = static_cast<int32_t*>(q);
+    const int64_t waves = static_cast<int64_t>(st->cus) * kMaxWavesPerCu;
+    e = hipMalloc(&q, sizeof(int32_t) * static_cast<size_t>(waves * gm::heavy_list_entries()));
+    if (e != hipSuccess) return from_hip(e);
+    ws.heavy = static_cast<int32_t*>(q);
+    ws.heavy_waves = waves;
   }
   if (ws.cap < nvec) {
     if (ws.list) (void)hipFree(ws.list);
@@ -172,7 +184,7 @@ gm_status sketch_common(const int32_t* indices, const float* weights, const int6
   if (s != GM_OK) return s;
   return from_hip(gm::launch_fastgm(a, g_pos_bits, g_t0_scale, g_map_load, g_republish,
                                     g_seg_rest, g_small_waves, ws->list, ws->plan, ws->big,
-                                    ws->pool, kPoolCap, st->cus,
+                                    ws->pool, kPoolCap, ws->heavy, ws->heavy_waves, st->cus,
                                     g_stats ? st->stats : nullptr, stream));
 }
 
@@ -373,6 +385,7 @@ void gm_release_stream(hipStream_t stream) {
   if (it->second.big) (void)hipFree(it->second.big);
   if (it->second.plan) (void)hipFree(it->second.plan);
   if (it->second.pool) (void)hipFree(it->second.pool);
+  if (it->second.heavy) (void)hipFree(it->second.heavy);
   st.plans.erase(it);
 }
 
@@ -393,6 +406,7 @@ void gm_release(void) {
       if (kv.second.big) (void)hipFree(kv.second.big);
       if (kv.second.plan) (void)hipFree(kv.second.plan);
       if (kv.second.pool) (void)hipFree(kv.second.pool);
+      if (kv.second.heavy) (void)hipFree(kv.second.heavy);
     }
     st.plans.clear();
   }

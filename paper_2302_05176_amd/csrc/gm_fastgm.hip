@@ -58,7 +58,11 @@
 namespace gm {
 
 constexpr int kMapSlots = 16;   // per-lane displaced-position table
-constexpr int kHeavyCap = 128;  // per-wave list of elements handed to the segment path
+// Per-wave list (device memory) of elements handed to the segment path.  The
+// segment path runs when the light path has drained (list nearly full, or the
+// walk is over), so that its dense permutations can reuse the LDS of the
+// light path's queue and tables.
+constexpr int kHeavyCapG = 1024;
 constexpr int kQueueCap = 64;   // per-wave candidate queue (one probe pass)
 // Vectors are grouped by size class (small, medium, big) and k class
 // (k <= 256, 1024, 2048, 4096) so that each persistent kernel sizes its LDS
@@ -116,6 +120,8 @@ struct FastArgs {
   int32_t cls;
   int32_t lds_k;        // register-array size this launch's LDS is laid out for
   unsigned long long* stats;  // optional counters (nullptr: off)
+  int32_t* heavy;       // kHeavyCapG entries per resident wave
+  int64_t heavy_waves;  // waves the heavy buffer has room for
 };
 
 // Optional per-call counters (summed over the launch), indices:
@@ -262,12 +268,22 @@ __device__ __forceinline__ void fy_batch(std::integer_sequence<int, Ls...>, int 
 }
 
 template <int G>
-__device__ void segment_walk(const VecCtx& c, const lds_u32* heavy, int nheavy, lds_u16* pm_all,
-                             int pm_stride, uint32_t& hgen, double& T) {
+__device__ void segment_walk(const VecCtx& c, const int32_t* heavy, int nheavy, lds_u16* pm_all,
+                             int pm_stride, double& T) {
   const int lane = __lane_id();
   const int row = lane / G;
   const int li = lane % G;
   lds_u16* pm = pm_all + row * pm_stride;
+  // The permutations share LDS with the light path: start from zeros
+  // (generation 0 reads as the identity everywhere).
+  {
+    lds_u64* z8 = reinterpret_cast<lds_u64*>(pm_all);
+    const int n8 = (kWave / G) * pm_stride / 4;
+    for (int q2 = lane; q2 < n8; q2 += kWave) z8[q2] = 0ull;
+  }
+  uint32_t hgen = 0;
+  // the list was written by this wave's lanes with vector stores
+  __threadfence_block();
   const int k = c.k;
   bool active = false;
   uint32_t hpos = 0;
@@ -285,7 +301,7 @@ __device__ void segment_walk(const VecCtx& c, const lds_u32* heavy, int nheavy, 
       const uint64_t below = row == 0 ? 0ull : (~0ull >> (64 - row * G));
       const int slot = next + __popcll(idle & below);
       if (!active && slot < nheavy) {
-        hpos = heavy[slot];
+        hpos = static_cast<uint32_t>(heavy[slot]);
         ind = c.idx[hpos];
         r = 1.0 / static_cast<double>(c.w[hpos]);
         P = mix(c.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(ind)));
@@ -403,12 +419,15 @@ __host__ __device__ constexpr size_t queue_bytes() { return kQueueCap * (8 + 8 +
 //      the threshold, the element joins the queue;
 //  (b) lanes without an element pop one from the queue and continue its walk
 //      from step 2; every active lane draws one arrival.
-// Elements whose displaced-position table fills up are listed in `heavy`
-// and walked on the segment path when the list is nearly full or at the end.
+// Elements expected to walk long, and those whose displaced-position table
+// fills up, are listed in `hl` (device memory) for the segment path.  That
+// path runs once nothing is in flight on the light path -- at the end of the
+// walk, or earlier when the list is nearly full (probing then pauses until
+// the queue and the lanes drain) -- and reuses the LDS of the queue and the
+// tables for its permutations; the tables are cleared afterwards.
 template <int G>
-__device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, lds_u32* heavy,
-                          lds_u16* pm, int pm_stride, uint32_t& hgen, lds_u32* mp,
-                          uint32_t& stamp, const Queue& q) {
+__device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, int32_t* hl, lds_u16* pm,
+                          int pm_stride, lds_u32* mp, uint32_t& stamp, const Queue& q) {
   const int lane = __lane_id();
   const double c1 = 1.0 / static_cast<double>(c.k);
   bool have = false;
@@ -439,8 +458,12 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, lds_u32* h
   }
   unsigned arrivals = 0, kept = 0, started = 0;
   while (true) {
+    // Until the drain: one probe pass and one overflow batch (128) per
+    // iteration; after it, at most one append per element in flight or
+    // queued (128).
+    const bool draining = nheavy > kHeavyCapG - 4 * kWave;
     // (a) probe pass
-    if (more && kQueueCap - (qtail - qhead) >= kWave) {
+    if (!draining && more && kQueueCap - (qtail - qhead) >= kWave) {
       const bool inb = pbase + lane < c.n;
       const int e = pf_p;          // position in the vector
       const float wv = pf_w;
@@ -469,7 +492,7 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, lds_u32* h
           pj = randint(draw(pP, kTagShuffle, 1u), 1, c.k);
           reg_update(c, pj - 1, t, static_cast<uint32_t>(e), pi);
           // Arrivals still to come before T arrive at rate about k v: a walk
-          // expected to outgrow the lane's table goes to the segment path now.
+          // expected to outgrow the lane's table goes to the segment path.
           const bool longwalk =
               static_cast<double>(c.k) * static_cast<double>(wv) * (T - t) > c.seg_rest;
           seg = c.k > 1 && longwalk;
@@ -477,7 +500,7 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, lds_u32* h
         }
       }
       const uint64_t sm = __ballot(seg);
-      if (seg) heavy[nheavy + __popcll(sm & lanemask_lt())] = static_cast<uint32_t>(e);
+      if (seg) hl[nheavy + __popcll(sm & lanemask_lt())] = e;
       nheavy += __popcll(sm);
       const uint64_t km = __ballot(keep);
       if (keep) {
@@ -491,10 +514,6 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, lds_u32* h
       }
       qtail += __popcll(km);
       more = pbase < c.n;
-      if (nheavy > kHeavyCap - kWave) {
-        segment_walk<G>(c, heavy, nheavy, pm, pm_stride, hgen, T);
-        nheavy = 0;
-      }
     }
     // (b) refill idle lanes from the queue
     const uint64_t need = __ballot(!have);
@@ -532,7 +551,8 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, lds_u32* h
       qhead += npop < avail ? npop : avail;
     }
     const bool any_have = __ballot(have) != 0;
-    const bool done = !any_have && !more && qtail == qhead;
+    // nothing in flight on the light path
+    const bool idle = !any_have && qtail == qhead;
     bool overflow = false;
     if (any_have) {
       if (have) {
@@ -579,17 +599,22 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, lds_u32* h
         T = fmin(T, wave_max_register(c));
     }
     const uint64_t om = __ballot(overflow);
-    if (overflow) heavy[nheavy + __popcll(om & lanemask_lt())] = pos;
+    if (overflow) hl[nheavy + __popcll(om & lanemask_lt())] = static_cast<int32_t>(pos);
     nheavy += __popcll(om);
-    if (done && pend) {
-      contest_check(c, pend_old, pend_pk);
-      pend = false;
+    if (idle && (draining || !more)) {
+      if (pend) {
+        contest_check(c, pend_old, pend_pk);
+        pend = false;
+      }
+      if (nheavy > 0) {
+        segment_walk<G>(c, hl, nheavy, pm, pm_stride, T);
+        nheavy = 0;
+        // the permutations overwrote the tables: clear them, restart stamps
+        for (int s = 0; s < kMapSlots; ++s) mp[s * kWave] = 0u;
+        stamp = 0u;
+      }
+      if (!more) break;
     }
-    if (done || nheavy > kHeavyCap - kWave) {
-      segment_walk<G>(c, heavy, nheavy, pm, pm_stride, hgen, T);
-      nheavy = 0;
-    }
-    if (done) break;
   }
   if (c.stats) {
     const int a = wave_sum_i32(static_cast<int>(arrivals));
@@ -614,12 +639,21 @@ __host__ __device__ constexpr int perm_stride(int k_max) { return ((k_max + 1 + 
 
 // Lanes per segment of the segment path: 16 (four elements per wave) while
 // four dense permutations stay small, else the whole wave.
-__host__ __device__ constexpr int segment_lanes(int k_max) { return k_max <= 2048 ? 16 : 64; }
+__host__ __device__ constexpr int segment_lanes(int k_max) { return k_max <= 1024 ? 16 : 64; }
 
+__host__ __device__ constexpr size_t light_lds_bytes() {
+  return queue_bytes() + static_cast<size_t>(kMapSlots) * kWave * 4;
+}
+
+__host__ __device__ constexpr size_t perm_lds_bytes(int k_max) {
+  return static_cast<size_t>(kWave / segment_lanes(k_max)) * perm_stride(k_max) * 2;
+}
+
+// Per-wave LDS: the light path's queue and tables, or (at other times) the
+// segment path's permutations, whichever is larger; 16-byte multiple.
 __host__ __device__ constexpr size_t wave_lds_bytes(int k_max) {
-  return queue_bytes() + static_cast<size_t>(kMapSlots) * kWave * 4 +
-         static_cast<size_t>(kWave / segment_lanes(k_max)) * perm_stride(k_max) * 2 +
-         kHeavyCap * 4;
+  return ((light_lds_bytes() > perm_lds_bytes(k_max) ? light_lds_bytes() : perm_lds_bytes(k_max)) +
+          15) / 16 * 16;
 }
 
 size_t fastgm_lds_bytes(int k_max, int waves) {
@@ -638,8 +672,7 @@ struct FgShared {
 template <int W, int G>
 __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, FgShared& sh,
                               lds_u64* packed, lds_u64* fullkey, lds_u16* pm, int pm_stride,
-                              uint32_t& hgen, lds_u32* heavy, lds_u32* mp, uint32_t& stamp,
-                              const Queue& q) {
+                              int32_t* hl, lds_u32* mp, uint32_t& stamp, const Queue& q) {
   constexpr int kBlock = W * kWave;
   const SketchArgs& p = fa.s;
   const int tid = threadIdx.x;
@@ -729,7 +762,7 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   double T = max_exp_quantile(d.k) * fa.t0_scale / S;
   bool resolve = false;
   for (int pass = 0;; ++pass) {
-    walk_wave<G>(c, cursor, T, heavy, pm, pm_stride, hgen, mp, stamp, q);
+    walk_wave<G>(c, cursor, T, hl, pm, pm_stride, mp, stamp, q);
     __syncthreads();
     if (resolve) break;
     bool miss = false;
@@ -774,7 +807,8 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
 // Persistent kernel of one size class: workgroups of W waves pull vector ids
 // from the class list until it is exhausted.
 template <int W, int G>
-__global__ __launch_bounds__(W * kWave) void fastgm_class_kernel(FastArgs fa) {
+__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(3)))
+void fastgm_class_kernel(FastArgs fa) {
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ FgShared sh;
   const int k_max = fa.lds_k;
@@ -790,18 +824,15 @@ __global__ __launch_bounds__(W * kWave) void fastgm_class_kernel(FastArgs fa) {
   q.pos = reinterpret_cast<lds_u32*>(wave_base + kQueueCap * 24);
   q.ind = reinterpret_cast<lds_i32*>(wave_base + kQueueCap * 28);
   q.j1 = reinterpret_cast<lds_u32*>(wave_base + kQueueCap * 32);
-  GM_LDS unsigned char* rest = wave_base + queue_bytes();
-  lds_u32* mp_base = reinterpret_cast<lds_u32*>(rest);
-  lds_u16* pm = reinterpret_cast<lds_u16*>(rest + kMapSlots * kWave * 4);
+  lds_u32* mp_base = reinterpret_cast<lds_u32*>(wave_base + queue_bytes());
+  // the segment path's permutations reuse the same bytes
+  lds_u16* pm = reinterpret_cast<lds_u16*>(wave_base);
   const int pm_stride = perm_stride(k_max);
-  const int pm_bytes = (kWave / G) * pm_stride * 2;
-  lds_u32* heavy = reinterpret_cast<lds_u32*>(rest + kMapSlots * kWave * 4 + pm_bytes);
+  int32_t* hl = fa.heavy + (static_cast<int64_t>(blockIdx.x) * W + threadIdx.x / kWave) * kHeavyCapG;
   const int lane = threadIdx.x % kWave;
   lds_u32* mp = mp_base + lane;
   for (int s = 0; s < kMapSlots; ++s) mp[s * kWave] = 0u;
-  for (int q2 = lane; q2 < (kWave / G) * pm_stride; q2 += kWave) pm[q2] = 0;
   uint32_t stamp = 0;
-  uint32_t hgen = 0;
 
   const PlanState* plan = fa.plan;
   const int count = plan->count[fa.cls];
@@ -816,8 +847,7 @@ __global__ __launch_bounds__(W * kWave) void fastgm_class_kernel(FastArgs fa) {
     const BigInfo* bi =
         (fa.cls >= kBigFirst && fa.big) ? &fa.big[plan->offset[fa.cls] - plan->offset[kBigFirst] + t]
                                         : nullptr;
-    sketch_vector<W, G>(fa, list[t], bi, sh, packed, fullkey, pm, pm_stride, hgen, heavy, mp,
-                        stamp, q);
+    sketch_vector<W, G>(fa, list[t], bi, sh, packed, fullkey, pm, pm_stride, hl, mp, stamp, q);
   }
 }
 
@@ -1034,7 +1064,8 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
 // LDS (160 KB per CU).
 int class_waves(int sc, int k_max, int small_waves) {
   int want = sc == 0 ? 1 : (sc == 1 ? 4 : 8);
-  if (sc == 0 && k_max > 512) want = k_max > 2048 ? 4 : 2;
+  if (sc == 0 && k_max > 256) want = k_max > 2048 ? 8 : 4;
+  if (sc == 1 && k_max > 2048) want = 8;
   if (sc == 0 && small_waves > 0) want = small_waves;
   int w = want;
   while (w > 1 && fastgm_lds_bytes(k_max, w) + sizeof(FgShared) > 160 * 1024) w /= 2;
@@ -1165,6 +1196,8 @@ static hipError_t launch_class(const FastArgs& fa, int cus, hipStream_t stream) 
   }
   int64_t grid = static_cast<int64_t>(cus) * per_cu;
   if (grid > fa.s.nvec) grid = fa.s.nvec;
+  if (grid * W > fa.heavy_waves) grid = fa.heavy_waves / W;  // room in the heavy buffer
+  if (grid < 1) return hipErrorInvalidValue;
   hipEvent_t ta = nullptr;
   const int tid = timing_begin("fastgm_class_kernel<" + std::to_string(W) + ", " +
                                    std::to_string(G) + ">",
@@ -1192,9 +1225,12 @@ constexpr int64_t kLimM = 32768;
 
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
                          int republish, double seg_rest, int small_waves, int32_t* list,
-                         void* plan, void* big, int32_t* pool, int64_t pool_cap, int cus,
+                         void* plan, void* big, int32_t* pool, int64_t pool_cap,
+                         int32_t* heavy, int64_t heavy_waves, int cus,
                          unsigned long long* stats, hipStream_t stream) {
   FastArgs fa;
+  fa.heavy = heavy;
+  fa.heavy_waves = heavy_waves;
   fa.big = static_cast<BigInfo*>(big);
   fa.pool = pool;
   fa.pool_cap = pool_cap;
@@ -1240,6 +1276,7 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
 }
 
 size_t plan_state_bytes() { return sizeof(PlanState); }
+int64_t heavy_list_entries() { return kHeavyCapG; }
 size_t big_info_bytes() { return sizeof(BigInfo); }
 
 }  // namespace gm
