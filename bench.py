@@ -31,20 +31,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one
-# full-rate VALU lane-operation per lane per cycle.
+# VALU issue peak of MI355X in f64-rate lane-cycles: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz (the FP64 vector rate, 78.6 TFLOP/s counting an FMA as 2).
+# On gfx950 FP64 add/mul/fma, 32-bit integer multiplies and 64-bit shifts issue
+# at this rate (1 slot), simple 32-bit ALU ops at twice it (0.5 slot), the
+# FP64 reciprocal at a quarter of it (4 slots) -- rates measured with
+# dependent-free instruction streams on MI355X.
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
-# Issue slots of one arrival of the draw specification as compiled for gfx950
-# (two splitmix64 hashes, the uniform, -ln, the c_z division, the fma, the key
-# multiply, the Fisher-Yates target): 106 VALU instructions, 15 of them
-# quarter-rate (32-bit integer multiplies, f64 reciprocal) counted 4 times.
-ARRIVAL_SLOTS = 151
-# One plain key (hash, uniform, -ln, multiply, compare): 88 VALU instructions,
-# 7 quarter-rate.
-PLAIN_KEY_SLOTS = 109
+# Slots of one arrival of the draw specification as compiled for gfx950 (two
+# splitmix64 hashes, the uniform, -ln with its division, the c_z division, the
+# fma, the key multiply, the Fisher-Yates target): 106 VALU instructions,
+# 100 slots.  A straight-line loop of arrivals runs at 3.3e11 arrivals/s
+# (119 lane-cycles each), 84% of this count at the peak.
+ARRIVAL_SLOTS = 100
+# One plain key with its register compare (hash, uniform, -ln, multiply,
+# lexicographic min): 88 VALU instructions, 81 slots.
+PLAIN_KEY_SLOTS = 81
 HBM_PEAK = 8.0e12
-DOMINANT = "fastgm_class_kernel<1, 16>"
-SMALL_LIMIT = 2048   # vectors of at most this many entries go to the kernel above
+# The FastGM launch that takes most of a k <= 256 step: every vector of at
+# most 32768 entries (larger ones are prepared by grid-wide passes and walked
+# by another launch).
+DOMINANT = "fastgm_class_kernel<4, 16>"
+SMALL_LIMIT = 32768
 
 
 def harmonic(k: int) -> float:
@@ -244,7 +252,9 @@ def bench_batch(args):
         slots = PLAIN_KEY_SLOTS
         unit_name = "keys (k n+)"
         vec_bytes = 8.0 * nnz + 8.0 * (args.nvec + 1) + 12.0 * regs
-    tot_ms, launches = kt.get(kern, (0.0, 0))
+    # the library names each FastGM launch after its kernel and the class it
+    # drains; at k <= 256 the dominant kernel drains class 0 only
+    tot_ms, launches = kt.get(kern + " [class 0]" if args.form == "fastgm" else kern, (0.0, 0))
     kern_s = tot_ms / launches / 1e3 if launches else ev_ms / 1e3
     achieved = units * slots / kern_s
     traffic = committed_traffic(kern, f"batch_k{k}_{args.form}")
@@ -252,7 +262,8 @@ def bench_batch(args):
         "bound": "alu",
         "achieved": achieved / 1e12,
         "peak": PEAK_VALU_OPS / 1e12,
-        "unit": "TOPS (VALU lane-ops/s: algorithmic units x issue slots per unit)",
+        "unit": "TOP/s",
+        "op": "f64-rate VALU lane-cycle (algorithmic units x slots per unit)",
         "frac": achieved / PEAK_VALU_OPS,
         "traffic": traffic,
         "kernel": kern,

@@ -196,8 +196,9 @@ gm_status gm_reset_data_errors(hipStream_t stream);
  *                        exceeds this goes to the segment path straight
  *                        from its first arrival, 0..1000000 (0: every
  *                        continuing element does).
- *   GM_OPT_SMALL_WAVES   [0] waves that share one small vector (0: chosen
- *                        from k; else 1, 2, 4 or 8).
+ *   GM_OPT_SMALL_WAVES   [0] waves per workgroup of the kernels for vectors
+ *                        of up to 32768 entries (0: chosen from k; else
+ *                        1, 2, 4 or 8).
  *   GM_OPT_TIMING        [0] 1 brackets every sketch-kernel launch with HIP
  *                        events on its stream (read with gm_get_timing).
  *   GM_OPT_STATS         [0] 1 makes FastGM calls accumulate work counters

@@ -15,10 +15,10 @@ hipError_t launch_plain(const SketchArgs& p, hipStream_t stream);
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
                          int republish, double seg_rest, int small_waves, int32_t* list,
                          void* plan, void* big, int32_t* pool, int64_t pool_cap,
-                         int32_t* heavy, int64_t heavy_waves, int cus,
+                         void* heavy, int64_t heavy_waves, int cus,
                          unsigned long long* stats, hipStream_t stream);
 size_t plan_state_bytes();
-int64_t heavy_list_entries();
+int64_t heavy_list_bytes();
 void timing_enable(bool on);
 int timing_collect(int n, char (*names)[64], double* ms, long long* launches);
 void timing_reset();
@@ -51,12 +51,14 @@ struct PlanWorkspace {
   int64_t cap = 0;
   void* plan = nullptr;
   int32_t* pool = nullptr;
-  int32_t* heavy = nullptr;   // per-wave heavy-element lists of the FastGM walk
+  void* heavy = nullptr;      // per-wave heavy-element lists of the FastGM walk
   int64_t heavy_waves = 0;
 };
 
-// Resident waves per CU the heavy lists are sized for (2048 threads / 64).
-constexpr int kMaxWavesPerCu = 32;
+// Resident waves per CU the heavy lists are sized for: the FastGM kernels
+// need more than 128 VGPRs, so at most 3 waves per SIMD (a launch that could
+// hold more is trimmed to this).
+constexpr int kMaxWavesPerCu = 12;
 
 constexpr int kStatSlots = 16;
 
@@ -130,9 +132,9 @@ gm_status plan_workspace(DeviceState* st, hipStream_t stream, int64_t nvec, Plan
     if (e != hipSuccess) return from_hip(e);
     ws.pool = static_cast<int32_t*>(q);
     const int64_t waves = static_cast<int64_t>(st->cus) * kMaxWavesPerCu;
-    e = hipMalloc(&q, sizeof(int32_t) * static_cast<size_t>(waves * gm::heavy_list_entries()));
+    e = hipMalloc(&q, static_cast<size_t>(waves * gm::heavy_list_bytes()));
     if (e != hipSuccess) return from_hip(e);
-    ws.heavy = static_cast<int32_t*>(q);
+    ws.heavy = q;
     ws.heavy_waves = waves;
   }
   if (ws.cap < nvec) {

@@ -9,10 +9,12 @@
 // maximum register y* (FastPrune): its later arrivals are larger still and
 // cannot change any register, so the result equals the unpruned one.
 //
-// GPU mapping.  A planner kernel sorts the vectors into three size classes
-// (and, inside a class, by decreasing size); one persistent kernel per class
-// drains its list through an atomic work counter.  A vector is handled by one
-// workgroup of W waves (W grows with the class) that share its registers:
+// GPU mapping.  A planner kernel sorts the vectors into classes by size (up
+// to 32768 entries, or big) and k range, and inside a class by decreasing
+// size; one persistent kernel per class drains its list through an atomic
+// work counter.  A large vector is handled by a workgroup of W waves that
+// share its registers; when the registers are small (k <= 256), vectors of
+// fewer than 2048 entries are handled by one wave each:
 //  * Registers live in LDS.  A register is two 64-bit words: `packed` holds
 //    the top bits of the key (positive doubles order like their bit patterns)
 //    above a pos_bits-wide entry position, updated by 64-bit LDS atomic-min;
@@ -62,16 +64,16 @@ constexpr int kMapSlots = 16;   // per-lane displaced-position table
 // segment path runs when the light path has drained (list nearly full, or the
 // walk is over), so that its dense permutations can reuse the LDS of the
 // light path's queue and tables.
-constexpr int kHeavyCapG = 1024;
+constexpr int kHeavyCapG = 512;
 constexpr int kQueueCap = 64;   // per-wave candidate queue (one probe pass)
-// Vectors are grouped by size class (small, medium, big) and k class
-// (k <= 256, 1024, 2048, 4096) so that each persistent kernel sizes its LDS
-// for its own k range.  Class id = size_class * kKClasses + k_class; the big
-// classes (size class 2) are contiguous in the planner's list.
-constexpr int kSizeClasses = 3;
+// Vectors are grouped by size class (up to kLimM entries, and big) and k
+// class (k <= 256, 1024, 2048, 4096) so that each persistent kernel sizes its
+// LDS for its own k range.  Class id = size_class * kKClasses + k_class; the
+// big classes (size class 1) are contiguous in the planner's list.
+constexpr int kSizeClasses = 2;
 constexpr int kKClasses = 4;
 constexpr int kNumClasses = kSizeClasses * kKClasses;
-constexpr int kBigFirst = 2 * kKClasses;
+constexpr int kBigFirst = kKClasses;
 
 __host__ __device__ constexpr int kclass_hi(int kc) { return kc == 0 ? 256 : (kc == 1 ? 1024 : (kc == 2 ? 2048 : 4096)); }
 
@@ -79,6 +81,23 @@ __host__ __device__ inline int kclass_of(int32_t k) {
   return k <= 256 ? 0 : (k <= 1024 ? 1 : (k <= 2048 ? 2 : 3));
 }
 constexpr int kPlanBins = 32;   // size sub-bins per class (log2 of n)
+
+// An element handed to the segment path, with the state of its walk so far:
+// after z steps the order statistic is O and the displaced positions are the
+// nent entries (pos-1) << 12 | (value-1); the segment path continues from
+// step z + 1.
+struct HeavyRec {
+  uint64_t P;      // hash prefix
+  double r;        // 1 / v
+  double O;        // O_z
+  int32_t pos;     // entry position in the vector
+  int32_t ind;     // element index
+  int32_t z;       // steps done
+  int32_t nent;
+  uint32_t ent[16];
+  uint32_t pad[6];
+};
+static_assert(sizeof(HeavyRec) == 128, "heavy record layout");
 
 struct PlanState {
   int count[kNumClasses];
@@ -120,7 +139,8 @@ struct FastArgs {
   int32_t cls;
   int32_t lds_k;        // register-array size this launch's LDS is laid out for
   unsigned long long* stats;  // optional counters (nullptr: off)
-  int32_t* heavy;       // kHeavyCapG entries per resident wave
+  HeavyRec* heavy;      // kHeavyCapG records per resident wave
+  int64_t wave_lim;     // vectors of at most this many entries: one wave each (0: none)
   int64_t heavy_waves;  // waves the heavy buffer has room for
 };
 
@@ -268,7 +288,7 @@ __device__ __forceinline__ void fy_batch(std::integer_sequence<int, Ls...>, int 
 }
 
 template <int G>
-__device__ void segment_walk(const VecCtx& c, const int32_t* heavy, int nheavy, lds_u16* pm_all,
+__device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy, lds_u16* pm_all,
                              int pm_stride, double& T) {
   const int lane = __lane_id();
   const int row = lane / G;
@@ -301,17 +321,24 @@ __device__ void segment_walk(const VecCtx& c, const int32_t* heavy, int nheavy, 
       const uint64_t below = row == 0 ? 0ull : (~0ull >> (64 - row * G));
       const int slot = next + __popcll(idle & below);
       if (!active && slot < nheavy) {
-        hpos = static_cast<uint32_t>(heavy[slot]);
-        ind = c.idx[hpos];
-        r = 1.0 / static_cast<double>(c.w[hpos]);
-        P = mix(c.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(ind)));
-        O = 0.0;
-        z0 = 1;
+        const HeavyRec* hr = heavy + slot;
+        hpos = static_cast<uint32_t>(hr->pos);
+        ind = hr->ind;
+        r = hr->r;
+        P = hr->P;
+        O = hr->O;
+        z0 = hr->z + 1;
+        const int nent = hr->nent;
         active = true;
         ++elems;
         hgen = hgen == 7u ? 1u : hgen + 1u;
         if (hgen == 1u)
           for (int q = li; q <= k; q += G) pm[q] = 0;
+        // the displaced positions of the walk so far
+        for (int q = li; q < nent; q += G) {
+          const uint32_t e = hr->ent[q];
+          pm[(e >> 12) + 1] = static_cast<uint16_t>((hgen << 13) | ((e & 0xFFFu) + 1));
+        }
       }
       const int ni = __popcll(idle);
       next += ni < nheavy - next ? ni : nheavy - next;
@@ -345,7 +372,12 @@ __device__ void segment_walk(const VecCtx& c, const int32_t* heavy, int nheavy, 
       disp = (ez >> 13) == hgen ? (ez & 0x1FFFu) : static_cast<uint32_t>(z);
     }
     bool killed = false;
-    fy_batch<G>(std::make_integer_sequence<int, G>{}, li, f, j, z, cval, disp, killed);
+    // The lane-order tests of the swap steps are cheap compares; keep the
+    // compiler from hoisting them into per-step lane masks held (and
+    // spilled) in scalar registers across the loop.
+    int li_v = li;
+    asm volatile("" : "+v"(li_v));
+    fy_batch<G>(std::make_integer_sequence<int, G>{}, li_v, f, j, z, cval, disp, killed);
     if (li < f && !killed) pm[j] = static_cast<uint16_t>((hgen << 13) | disp);
     if (li < f) reg_update(c, static_cast<int32_t>(cval) - 1, t, hpos, ind);
     const bool finished = f < nval || z0 + G > k;
@@ -426,7 +458,7 @@ __host__ __device__ constexpr size_t queue_bytes() { return kQueueCap * (8 + 8 +
 // the queue and the lanes drain) -- and reuses the LDS of the queue and the
 // tables for its permutations; the tables are cleared afterwards.
 template <int G>
-__device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, int32_t* hl, lds_u16* pm,
+__device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* hl, lds_u16* pm,
                           int pm_stride, lds_u32* mp, uint32_t& stamp, const Queue& q) {
   const int lane = __lane_id();
   const double c1 = 1.0 / static_cast<double>(c.k);
@@ -500,7 +532,18 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, int32_t* h
         }
       }
       const uint64_t sm = __ballot(seg);
-      if (seg) hl[nheavy + __popcll(sm & lanemask_lt())] = e;
+      if (seg) {
+        // one step done: position j1 holds value 1
+        HeavyRec* hr = hl + nheavy + __popcll(sm & lanemask_lt());
+        hr->P = pP;
+        hr->r = pr;
+        hr->O = pO;
+        hr->pos = e;
+        hr->ind = pi;
+        hr->z = 1;
+        hr->nent = pj != 1 ? 1 : 0;
+        hr->ent[0] = static_cast<uint32_t>(pj - 1) << 12;
+      }
       nheavy += __popcll(sm);
       const uint64_t km = __ballot(keep);
       if (keep) {
@@ -558,8 +601,8 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, int32_t* h
       if (have) {
         ++z;
         const double E = exp1(draw(P, kTagArrival, static_cast<uint32_t>(z)));
-        O = fma(E, 1.0 / static_cast<double>(c.k - z + 1), O);
-        const double t = O * r;
+        const double On = fma(E, 1.0 / static_cast<double>(c.k - z + 1), O);
+        const double t = On * r;
         ++arrivals;
         if (pend) contest_check(c, pend_old, pend_pk);
         pend = false;
@@ -587,6 +630,7 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, int32_t* h
           if (overflow) {
             have = false;
           } else {
+            O = On;
             pend_pk = packed_key(c, t, pos);
             pend_old = reg_offer(c, static_cast<int32_t>(vj) - 1, t, pend_pk, ind);
             pend = c.mode == kWalkNormal;
@@ -599,7 +643,22 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, int32_t* h
         T = fmin(T, wave_max_register(c));
     }
     const uint64_t om = __ballot(overflow);
-    if (overflow) hl[nheavy + __popcll(om & lanemask_lt())] = static_cast<int32_t>(pos);
+    if (overflow) {
+      // hand the walk over after z - 1 steps, with its displaced positions
+      HeavyRec* hr = hl + nheavy + __popcll(om & lanemask_lt());
+      hr->P = P;
+      hr->r = r;
+      hr->O = O;
+      hr->pos = static_cast<int32_t>(pos);
+      hr->ind = ind;
+      hr->z = z - 1;
+      int ne = 0;
+      for (int s2 = 0; s2 < kMapSlots; ++s2) {
+        const uint32_t me = mp[s2 * kWave];
+        if ((me >> 24) == stamp) hr->ent[ne++] = me & 0xFFFFFFu;
+      }
+      hr->nent = ne;
+    }
     nheavy += __popcll(om);
     if (idle && (draining || !more)) {
       if (pend) {
@@ -656,8 +715,10 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int k_max) {
           15) / 16 * 16;
 }
 
-size_t fastgm_lds_bytes(int k_max, int waves) {
-  return 16 * static_cast<size_t>(k_max) + waves * wave_lds_bytes(k_max);
+// Dynamic LDS of a class kernel: reg_sets register arrays (one per wave when
+// waves take vectors of their own) and each wave's working area.
+size_t fastgm_lds_bytes(int k_max, int waves, int reg_sets) {
+  return 16 * static_cast<size_t>(k_max) * reg_sets + waves * wave_lds_bytes(k_max);
 }
 
 struct FgShared {
@@ -669,15 +730,37 @@ struct FgShared {
   unsigned long long wmax[16];
 };
 
-template <int W, int G>
+// Barrier of a group of GW waves (one wave: only keeps the compiler from
+// moving LDS accesses across it; a wave executes its LDS operations in order).
+template <int GW>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (GW == 1)
+    __builtin_amdgcn_wave_barrier();
+  else
+    __syncthreads();
+}
+
+template <int GW>
+__device__ __forceinline__ bool group_or(bool b) {
+  if constexpr (GW == 1) {
+    __builtin_amdgcn_wave_barrier();
+    return __ballot(b) != 0;
+  } else {
+    return __syncthreads_or(b) != 0;
+  }
+}
+
+// Sketch vector v with a group of GW waves: the whole workgroup (GW = W) or
+// a single wave (GW = 1) with its own registers and shared words.
+template <int GW, int G>
 __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, FgShared& sh,
                               lds_u64* packed, lds_u64* fullkey, lds_u16* pm, int pm_stride,
-                              int32_t* hl, lds_u32* mp, uint32_t& stamp, const Queue& q) {
-  constexpr int kBlock = W * kWave;
+                              HeavyRec* hl, lds_u32* mp, uint32_t& stamp, const Queue& q) {
+  constexpr int kBlock = GW * kWave;
   const SketchArgs& p = fa.s;
-  const int tid = threadIdx.x;
-  const int wave = tid / kWave;
-  const int lane = tid % kWave;
+  const int lane = threadIdx.x % kWave;
+  const int tid = GW == 1 ? lane : static_cast<int>(threadIdx.x);
+  const int wave = GW == 1 ? 0 : static_cast<int>(threadIdx.x) / kWave;
   const VecDesc d = vec_desc(p, v);
   const int32_t span = out_span(p, v, d);
   const int64_t n64 = d.b - d.a;
@@ -693,7 +776,7 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
       fullkey[j] = kInfBits;
     }
   }
-  __syncthreads();
+  group_sync<GW>();
   // Validation and the mass S = sum(v) (its rounding only moves T0); a big
   // vector had both done by the grid-wide pass.
   double part = 0.0;
@@ -704,7 +787,27 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
       badl = bi->bad != 0;
     }
   } else if (!bad0) {
-    for (int64_t e = d.a + tid; e < d.b; e += kBlock) {
+    // four independent loads per lane in flight per step (the pass is
+    // latency-bound otherwise)
+    constexpr int kU = 4;
+    int64_t e = d.a + tid;
+    for (; e + (kU - 1) * kBlock < d.b; e += kU * kBlock) {
+      int32_t iv[kU];
+      float wv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        iv[u] = p.idx[e + u * kBlock];
+        wv[u] = p.w[e + u * kBlock];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (iv[u] < 0 || !weight_valid(wv[u]))
+          badl = true;
+        else
+          part += static_cast<double>(wv[u]);
+      }
+    }
+    for (; e < d.b; e += kBlock) {
       const int32_t i = p.idx[e];
       const float wv = p.w[e];
       if (i < 0 || !weight_valid(wv))
@@ -716,9 +819,9 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   if (badl) sh.bad = 1;
   part = wave_sum_f64(part);
   if (lane == 0) sh.wsum[wave] = part;
-  __syncthreads();
+  group_sync<GW>();
   double S = 0.0;
-  for (int qq = 0; qq < W; ++qq) S += sh.wsum[qq];
+  for (int qq = 0; qq < GW; ++qq) S += sh.wsum[qq];
   if (sh.bad || !(S > 0.0)) {
     const bool bad = sh.bad != 0;
     for (int j = tid; j < span; j += kBlock) {
@@ -726,7 +829,7 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
       p.out_val[d.o + j] = bitsd(bad ? kNanBits : kInfBits);
     }
     if (bad && tid == 0) atomicAdd(p.err, 1ull);
-    __syncthreads();
+    group_sync<GW>();
     return;
   }
 
@@ -763,18 +866,18 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   bool resolve = false;
   for (int pass = 0;; ++pass) {
     walk_wave<G>(c, cursor, T, hl, pm, pm_stride, mp, stamp, q);
-    __syncthreads();
+    group_sync<GW>();
     if (resolve) break;
     bool miss = false;
     for (int j = tid; j < d.k; j += kBlock) miss |= fullkey[j] == kInfBits;
-    if (__syncthreads_or(miss)) {
+    if (group_or<GW>(miss)) {
       if (tid == 0) stat_add(fa.stats, kStPasses, 1);
       T = pass >= 8 ? bitsd(kInfBits) : T * 2.0;
       // above T0 the candidate list no longer covers every element
       c.gather = nullptr;
       c.n = static_cast<int32_t>(n64);
       if (tid == 0) sh.cursor = 0;
-      __syncthreads();
+      group_sync<GW>();
       continue;
     }
     if (sh.contest == 0) break;
@@ -786,37 +889,59 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
     for (int j = tid; j < d.k; j += kBlock) m = fullkey[j] > m ? fullkey[j] : m;
     m = wave_max_u64(m);
     if (lane == 0) sh.wmax[wave] = m;
-    __syncthreads();
+    group_sync<GW>();
     unsigned long long ystar = 0;
-    for (int qq = 0; qq < W; ++qq) ystar = sh.wmax[qq] > ystar ? sh.wmax[qq] : ystar;
+    for (int qq = 0; qq < GW; ++qq) ystar = sh.wmax[qq] > ystar ? sh.wmax[qq] : ystar;
     for (int j = tid; j < d.k; j += kBlock) packed[j] = ~0ull;
     if (tid == 0) sh.cursor = 0;
-    __syncthreads();
+    group_sync<GW>();
     c.mode = kWalkResolve;
     T = bitsd(ystar);
   }
   const unsigned long long pmask = (1ull << fa.pos_bits) - 1ull;
-  for (int j = tid; j < d.k; j += kBlock) {
-    const unsigned long long pk = packed[j];
-    p.out_idx[d.o + j] = resolve ? static_cast<int32_t>(pk) : c.idx[pk & pmask];
-    p.out_val[d.o + j] = bitsd(fullkey[j]);
+  // gather the winners' indices four registers at a time (loads in flight
+  // together), then store
+  constexpr int kU = 4;
+  for (int j0 = tid; j0 < d.k; j0 += kU * kBlock) {
+    int32_t oi[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int j = j0 + u * kBlock;
+      if (j < d.k) {
+        const unsigned long long pk = packed[j];
+        oi[u] = resolve ? static_cast<int32_t>(pk) : c.idx[pk & pmask];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int j = j0 + u * kBlock;
+      if (j < d.k) {
+        p.out_idx[d.o + j] = oi[u];
+        p.out_val[d.o + j] = bitsd(fullkey[j]);
+      }
+    }
   }
-  __syncthreads();
+  group_sync<GW>();
 }
 
-// Persistent kernel of one size class: workgroups of W waves pull vector ids
-// from the class list until it is exhausted.
+// Persistent kernel of one class: workgroups of W waves pull vector ids from
+// the class list (largest first) until it is exhausted.  A vector larger
+// than fa.wave_lim is sketched by the whole workgroup; once the list reaches
+// vectors of at most fa.wave_lim entries, every wave takes vectors of its own
+// (with its own registers), so that the last large vectors overlap with the
+// small ones instead of leaving the other workgroups idle.
 template <int W, int G>
 __global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(3)))
 void fastgm_class_kernel(FastArgs fa) {
   extern __shared__ __align__(16) unsigned char dyn[];
-  __shared__ FgShared sh;
+  __shared__ FgShared sh[W];
   const int k_max = fa.lds_k;
+  const int wave = threadIdx.x / kWave;
+  const int reg_sets = fa.wave_lim > 0 ? W : 1;
   GM_LDS unsigned char* base = (GM_LDS unsigned char*)(dyn);  // address-space cast
-  lds_u64* packed = reinterpret_cast<lds_u64*>(base);
-  lds_u64* fullkey = packed + k_max;
-  GM_LDS unsigned char* wave_base = reinterpret_cast<GM_LDS unsigned char*>(fullkey + k_max) +
-                                    (threadIdx.x / kWave) * wave_lds_bytes(k_max);
+  lds_u64* regs = reinterpret_cast<lds_u64*>(base);           // reg_sets x (packed, fullkey)
+  GM_LDS unsigned char* wave_base = reinterpret_cast<GM_LDS unsigned char*>(regs + 2 * k_max * reg_sets) +
+                                    wave * wave_lds_bytes(k_max);
   Queue q;
   q.P = reinterpret_cast<lds_u64*>(wave_base);
   q.r = reinterpret_cast<lds_f64*>(wave_base + kQueueCap * 8);
@@ -828,7 +953,7 @@ void fastgm_class_kernel(FastArgs fa) {
   // the segment path's permutations reuse the same bytes
   lds_u16* pm = reinterpret_cast<lds_u16*>(wave_base);
   const int pm_stride = perm_stride(k_max);
-  int32_t* hl = fa.heavy + (static_cast<int64_t>(blockIdx.x) * W + threadIdx.x / kWave) * kHeavyCapG;
+  HeavyRec* hl = fa.heavy + (static_cast<int64_t>(blockIdx.x) * W + wave) * kHeavyCapG;
   const int lane = threadIdx.x % kWave;
   lds_u32* mp = mp_base + lane;
   for (int s = 0; s < kMapSlots; ++s) mp[s * kWave] = 0u;
@@ -838,16 +963,33 @@ void fastgm_class_kernel(FastArgs fa) {
   const int count = plan->count[fa.cls];
   const int32_t* list = fa.list + plan->offset[fa.cls];
   int* next = &fa.plan->next[fa.cls];
+  int t = 0;
   for (;;) {
-    if (threadIdx.x == 0) sh.task = atomicAdd(next, 1);
+    if (threadIdx.x == 0) sh[0].task = atomicAdd(next, 1);
     __syncthreads();
-    const int t = sh.task;
+    t = sh[0].task;
     __syncthreads();
-    if (t >= count) break;
+    if (t >= count) return;
+    const int64_t v = list[t];
+    if (fa.wave_lim > 0 && fa.s.off[v + 1] - fa.s.off[v] <= fa.wave_lim) break;
     const BigInfo* bi =
         (fa.cls >= kBigFirst && fa.big) ? &fa.big[plan->offset[fa.cls] - plan->offset[kBigFirst] + t]
                                         : nullptr;
-    sketch_vector<W, G>(fa, list[t], bi, sh, packed, fullkey, pm, pm_stride, hl, mp, stamp, q);
+    sketch_vector<W, G>(fa, v, bi, sh[0], regs, regs + k_max, pm, pm_stride, hl, mp, stamp, q);
+  }
+  // one vector per wave from here on (wave 0 starts with the task in hand)
+  lds_u64* wpacked = regs + 2 * k_max * wave;
+  int mt = wave == 0 ? t : -1;
+  for (;;) {
+    if (mt < 0) {
+      int got = 0;
+      if (lane == 0) got = atomicAdd(next, 1);
+      mt = readlane_i32(got, 0);
+    }
+    if (mt >= count) break;
+    sketch_vector<1, G>(fa, list[mt], nullptr, sh[wave], wpacked, wpacked + k_max, pm, pm_stride,
+                        hl, mp, stamp, q);
+    mt = -1;
   }
 }
 
@@ -855,11 +997,10 @@ void fastgm_class_kernel(FastArgs fa) {
 // log2 size) with a counting sort, and resets the classes' work counters.
 constexpr int kPlanBlock = 1024;
 
-__device__ __forceinline__ int plan_bin(const SketchArgs& p, int64_t v, int64_t lim_s,
-                                        int64_t lim_m) {
+__device__ __forceinline__ int plan_bin(const SketchArgs& p, int64_t v, int64_t lim_m) {
   const int64_t n = p.off[v + 1] - p.off[v];
   const int32_t k = p.kvec ? p.kvec[v] : p.k_uniform;
-  const int sc = n <= lim_s ? 0 : (n <= lim_m ? 1 : 2);
+  const int sc = n <= lim_m ? 0 : 1;
   const int kc = (k >= 1 && k <= p.k_max) ? kclass_of(k) : 0;
   const int cls = sc * kKClasses + kc;
   const int lg = n > 0 ? 63 - __clzll(static_cast<unsigned long long>(n)) : 0;
@@ -869,13 +1010,13 @@ __device__ __forceinline__ int plan_bin(const SketchArgs& p, int64_t v, int64_t 
 __global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t* list,
                                                           PlanState* plan, BigInfo* big,
                                                           int64_t pool_cap, double t0_scale,
-                                                          int64_t lim_s, int64_t lim_m) {
+                                                          int64_t lim_m) {
   __shared__ int hist[kNumClasses * kPlanBins];
   __shared__ int base[kNumClasses * kPlanBins];
   const int tid = threadIdx.x;
   for (int b = tid; b < kNumClasses * kPlanBins; b += kPlanBlock) hist[b] = 0;
   __syncthreads();
-  for (int64_t v = tid; v < p.nvec; v += kPlanBlock) atomicAdd(&hist[plan_bin(p, v, lim_s, lim_m)], 1);
+  for (int64_t v = tid; v < p.nvec; v += kPlanBlock) atomicAdd(&hist[plan_bin(p, v, lim_m)], 1);
   __syncthreads();
   if (tid == 0) {
     int acc = 0;
@@ -893,7 +1034,7 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t*
   }
   __syncthreads();
   for (int64_t v = tid; v < p.nvec; v += kPlanBlock) {
-    const int b = plan_bin(p, v, lim_s, lim_m);
+    const int b = plan_bin(p, v, lim_m);
     list[atomicAdd(&base[b], 1)] = static_cast<int32_t>(v);
   }
   __syncthreads();
@@ -1059,17 +1200,23 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
   }
 }
 
-// Waves per workgroup of each size class: small vectors get one wave unless
-// the register array is large enough that waves should share it; limited by
-// LDS (160 KB per CU).
-int class_waves(int sc, int k_max, int small_waves) {
-  int want = sc == 0 ? 1 : (sc == 1 ? 4 : 8);
-  if (sc == 0 && k_max > 256) want = k_max > 2048 ? 8 : 4;
-  if (sc == 1 && k_max > 2048) want = 8;
+// Vectors of at most this many entries are sketched one per wave when the
+// register arrays are small enough for a set per wave (k <= 256); a power of
+// two minus one, so that it falls between the planner's log2 size bins.
+constexpr int64_t kWaveLim = 2047;
+
+// Waves per workgroup of a class (four, eight for k > 2048 and for big
+// vectors; halved while the LDS does not fit in 160 KB), and its one-wave
+// size limit.
+void class_shape(int sc, int k_max, int small_waves, int* waves, int64_t* wave_lim) {
+  int want = sc == 0 ? (k_max > 2048 ? 8 : 4) : 8;
   if (sc == 0 && small_waves > 0) want = small_waves;
+  const int64_t lim = (sc == 0 && k_max <= 256) ? kWaveLim : 0;
   int w = want;
-  while (w > 1 && fastgm_lds_bytes(k_max, w) + sizeof(FgShared) > 160 * 1024) w /= 2;
-  return w;
+  while (w > 1 && fastgm_lds_bytes(k_max, w, lim > 0 ? w : 1) + w * sizeof(FgShared) > 160 * 1024)
+    w /= 2;
+  *waves = w;
+  *wave_lim = lim;
 }
 
 // ---------------------------------------------------------------------------
@@ -1177,7 +1324,7 @@ struct OccKey {
 
 template <int W, int G>
 static hipError_t launch_class(const FastArgs& fa, int cus, hipStream_t stream) {
-  const size_t lds = fastgm_lds_bytes(fa.lds_k, W);
+  const size_t lds = fastgm_lds_bytes(fa.lds_k, W, fa.wave_lim > 0 ? W : 1);
   const void* fn = reinterpret_cast<const void*>(fastgm_class_kernel<W, G>);
   // occupancy per (kernel, LDS size), computed once
   static OccKey cache[64];
@@ -1199,8 +1346,9 @@ static hipError_t launch_class(const FastArgs& fa, int cus, hipStream_t stream) 
   if (grid * W > fa.heavy_waves) grid = fa.heavy_waves / W;  // room in the heavy buffer
   if (grid < 1) return hipErrorInvalidValue;
   hipEvent_t ta = nullptr;
+  // named as rocprofv3 names the kernel, plus the class it drains
   const int tid = timing_begin("fastgm_class_kernel<" + std::to_string(W) + ", " +
-                                   std::to_string(G) + ">",
+                                   std::to_string(G) + "> [class " + std::to_string(fa.cls) + "]",
                                stream, &ta);
   hipLaunchKernelGGL((fastgm_class_kernel<W, G>), dim3(static_cast<unsigned>(grid)), dim3(W * kWave),
                      lds, stream, fa);
@@ -1218,18 +1366,17 @@ static hipError_t launch_class_w(const FastArgs& fa, int waves, int cus, hipStre
   }
 }
 
-// Vectors of at most kLimS entries go one per wave; up to kLimM four waves
-// share one; larger ones take the widest workgroup that fits.
-constexpr int64_t kLimS = 2048;
+// Vectors above kLimM entries are "big": validated, summed and probed by
+// grid-wide passes first, then walked over their candidate lists.
 constexpr int64_t kLimM = 32768;
 
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
                          int republish, double seg_rest, int small_waves, int32_t* list,
                          void* plan, void* big, int32_t* pool, int64_t pool_cap,
-                         int32_t* heavy, int64_t heavy_waves, int cus,
+                         void* heavy, int64_t heavy_waves, int cus,
                          unsigned long long* stats, hipStream_t stream) {
   FastArgs fa;
-  fa.heavy = heavy;
+  fa.heavy = static_cast<HeavyRec*>(heavy);
   fa.heavy_waves = heavy_waves;
   fa.big = static_cast<BigInfo*>(big);
   fa.pool = pool;
@@ -1246,7 +1393,7 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
   hipEvent_t ta = nullptr;
   int tid = timing_begin("plan_kernel", stream, &ta);
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, stream, s, list, fa.plan, fa.big,
-                     pool_cap, t0_scale, kLimS, kLimM);
+                     pool_cap, t0_scale, kLimM);
   timing_end(tid, ta, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1266,7 +1413,8 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
       if (lo > s.k_max) break;
       fa.cls = sc * kKClasses + kc;
       fa.lds_k = s.k_max < kclass_hi(kc) ? s.k_max : kclass_hi(kc);
-      const int waves = class_waves(sc, fa.lds_k, small_waves);
+      int waves = 1;
+      class_shape(sc, fa.lds_k, small_waves, &waves, &fa.wave_lim);
       e = segment_lanes(fa.lds_k) == 16 ? launch_class_w<16>(fa, waves, cus, stream)
                                         : launch_class_w<64>(fa, waves, cus, stream);
       if (e != hipSuccess) return e;
@@ -1276,7 +1424,7 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
 }
 
 size_t plan_state_bytes() { return sizeof(PlanState); }
-int64_t heavy_list_entries() { return kHeavyCapG; }
+int64_t heavy_list_bytes() { return kHeavyCapG * static_cast<int64_t>(sizeof(HeavyRec)); }
 size_t big_info_bytes() { return sizeof(BigInfo); }
 
 }  // namespace gm
