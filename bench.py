@@ -132,7 +132,15 @@ def summarize_pmc(args):
             rec = json.load(f)
     except (OSError, ValueError):
         rec = {}
-    rec[workload] = {n: e for n, e in out.items() if "elementwise" not in n}
+    rec[workload] = {n: e for n, e in out.items() if "elementwise" not in n and "__amd" not in n}
+    rec["_commands"] = [
+        "cd /tmp && timeout -s KILL 90 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc_FETCH_SIZE -o run -- "
+        "python3 <repo>/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras --copy-bytes 1073741824",
+        "cd /tmp && timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <repo>/gpurun_out/pmc_WRITE_SIZE -o run -- "
+        "python3 <repo>/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras --copy-bytes 1073741824",
+        "python bench.py --summarize-pmc gpurun_out/pmc_FETCH_SIZE gpurun_out/pmc_WRITE_SIZE --copy-bytes 1073741824 --k 256",
+        "FETCH_SIZE and WRITE_SIZE are KiB per dispatch; each is scaled by copy_bytes / (what it reads for the "
+        "calibration elementwise kernel that reads and writes copy_bytes)"]
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1, sort_keys=True)
         f.write("\n")
