@@ -152,7 +152,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["batch", "single", "stream", "uneven", "serve"],
+    ap.add_argument("--workload", choices=["batch", "single", "stream", "uneven", "serve", "rates"],
                     default="batch")
     ap.add_argument("--form", choices=["fastgm", "plain"], default="fastgm")
     ap.add_argument("--k", type=int, default=256)
@@ -421,6 +421,29 @@ def bench_uneven(args):
                       "autotuned": tuned, "graph": True, "input_gen_s": gen_s}), flush=True)
 
 
+def bench_rates(args):
+    """Issue-rate ceiling of the per-arrival and per-key arithmetic: every lane
+    draws a long run of arrivals (or plain keys) of its own element with no
+    memory traffic; compared with the slot counts the roofline uses."""
+    import torch
+
+    import paper_2302_05176_amd as gm
+    dev = torch.device("cuda:0")
+    lanes = 1 << 21
+    out = torch.empty(lanes, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for what, slots in (("arrivals", ARRIVAL_SLOTS), ("keys", PLAIN_KEY_SLOTS)):
+        for steps in (256, 1024):
+            ms, _ = timed_steps(lambda: gm.rate_probe(what, lanes, steps, args.seed, out=out),
+                                max(2, args.steps // 4), 1, stream)
+            rate = lanes * steps / (ms / 1e3)
+            res[f"{what}_k{steps}"] = {"per_s": rate, "lane_cycles_each": PEAK_VALU_OPS / rate,
+                                      "slots_each": slots, "frac_of_peak": rate * slots / PEAK_VALU_OPS}
+    print(json.dumps({"workload": f"issue-rate probe: {lanes} lanes, one element each, no memory traffic",
+                      "peak_slots_per_s": PEAK_VALU_OPS, "results": res}), flush=True)
+
+
 def bench_serve(args):
     import numpy as np
     import torch
@@ -457,7 +480,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     {"batch": bench_batch, "single": bench_single, "stream": bench_stream,
-     "uneven": bench_uneven, "serve": bench_serve}[args.workload](args)
+     "uneven": bench_uneven, "serve": bench_serve, "rates": bench_rates}[args.workload](args)
 
 
 if __name__ == "__main__":

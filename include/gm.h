@@ -156,6 +156,20 @@ gm_status gm_wcard_est(const double *val, int64_t nvec, int32_t k, double *out,
                        hipStream_t stream);
 
 /*
+ * gm_rate_probe -- issue-rate probe for the roofline of the sketch kernels.
+ * Every one of `lanes` lanes draws `steps` (1..GM_K_MAX) arrivals
+ * (what = 0: Renyi prefix of Eq. (7)-(8) with the Fisher-Yates target, as
+ * the FastGM walk draws them, k = steps) or plain keys (what = 1: Eq. (1),
+ * registers 0..steps-1) of its own synthetic element, with no memory traffic
+ * but one fp64 result per lane in out[lanes] (device, caller-owned).  Time it
+ * with events on `stream`; the rate is the VALU ceiling of the per-arrival
+ * arithmetic.  Invalid what/steps or a null out with lanes > 0 ->
+ * GM_ERR_INVALID_ARG.
+ */
+gm_status gm_rate_probe(int32_t what, int64_t lanes, int32_t steps, uint64_t seed, double *out,
+                        hipStream_t stream);
+
+/*
  * gm_merge -- sketch of a union from sketches of its parts (Sec. 2.3):
  * register j of the result is the lexicographic (y, s) minimum over the r
  * input sketches' register j (r row-major sketches of k registers in
@@ -221,11 +235,14 @@ gm_status gm_set_option(gm_option opt, int64_t value);
 /*
  * gm_get_stats -- synchronises `stream`, then copies the first n (<= 16)
  * FastGM work counters of the current device, summed over calls made while
- * GM_OPT_STATS was 1: [0] vectors, [1] light-path wave iterations, [2] light
- * arrivals drawn, [3] of which at or below the pruning threshold, [4]
- * elements started on the light path, [5] elements moved to the
- * wave-cooperative path, [6] its 64-arrival batches, [7] extra passes after
- * an unfilled register, [8] exact index resolutions.
+ * GM_OPT_STATS was 1: [0] vectors, [1] light-path wave iterations, [2]
+ * probe and light arrivals drawn, [3] of which at or below the pruning
+ * threshold, [4] elements continued on the light path, [5] elements handed
+ * to the segment path, [6] its 16-lane (or 64-lane) batches, [7] extra
+ * passes after an unfilled register, [8] exact index resolutions; wave
+ * clock cycles (summed over waves) spent in [9] register init, validation
+ * and sum, [10] the first walk, [11] the segment path (part of [10] and
+ * [12]), [12] repeated walks, [13] completion checks and writeback.
  * gm_reset_stats -- synchronises `stream` and zeroes the counters.
  */
 gm_status gm_get_stats(int64_t *host_counters, int32_t n, hipStream_t stream);

@@ -158,6 +158,20 @@ def merge(idx, val, stream=None):
     return oi, ov
 
 
+def rate_probe(what: str, lanes: int, steps: int, seed: int = 1, out=None, stream=None):
+    """Issue-rate probe (gm_rate_probe): `lanes` lanes each draw `steps` FastGM
+    arrivals (what="arrivals") or plain keys (what="keys"); returns the
+    per-lane results (fp64, on the current device)."""
+    torch = _torch()
+    L = _native.load()
+    if out is None:
+        out = torch.empty(lanes, dtype=torch.float64, device=torch.device("cuda", torch.cuda.current_device()))
+    st = L.gm_rate_probe({"arrivals": 0, "keys": 1}[what], lanes, steps, seed,
+                         _dev(out, torch.float64, "out"), _stream(stream))
+    _native.check(st, "gm_rate_probe")
+    return out
+
+
 def autotune(indices, weights, offsets, k_max: int, seed: int, k_per_vec=None, out_offsets=None,
              out_idx=None, out_val=None, reps: int = 3, use_cache: bool = True, stream=None) -> dict:
     """Time this batch under the FastGM schedule options, apply the fastest

@@ -24,7 +24,7 @@ GM_K_MAX = 4096
 OPTIONS = {"pos_bits": 0, "t0_scale_ppm": 1, "map_load": 2, "republish": 3, "stats": 4,
            "seg_rest": 5, "small_waves": 6, "timing": 7}
 STATS = ["vectors", "iterations", "arrivals", "kept", "elements", "heavy", "heavy_batches",
-         "passes", "resolves"]
+         "passes", "resolves", "cyc_prep", "cyc_walk", "cyc_seg", "cyc_extra", "cyc_out"]
 
 _lib = None
 
@@ -64,6 +64,7 @@ def load() -> ctypes.CDLL:
     L.gm_jaccard_est_pairs.argtypes = [p, i64, i32, p, p, i64, p, p]
     L.gm_wcard_est.argtypes = [p, i64, i32, p, p]
     L.gm_merge.argtypes = [p, p, i64, i32, p, p, p]
+    L.gm_rate_probe.argtypes = [i32, i64, i32, u64, p, p]
     L.gm_get_data_errors.argtypes = [ctypes.POINTER(ctypes.c_int64), p]
     L.gm_reset_data_errors.argtypes = [p]
     L.gm_set_option.argtypes = [ctypes.c_int, i64]

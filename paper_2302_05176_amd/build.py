@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgm.so")
-SOURCES = ["gm_api.hip", "gm_plain.hip", "gm_fastgm.hip", "gm_estimators.hip", "gm_tune.cpp",
-           "gm_serve.cpp"]
+SOURCES = ["gm_api.hip", "gm_plain.hip", "gm_fastgm.hip", "gm_estimators.hip", "gm_rates.hip",
+           "gm_tune.cpp", "gm_serve.cpp"]
 HEADERS = ["gm_common.h", "gm_draw.h"]
 ARCH = os.environ.get("GM_OFFLOAD_ARCH", "gfx950")
 

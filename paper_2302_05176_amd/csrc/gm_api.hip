@@ -33,6 +33,8 @@ hipError_t launch_wcard(const double* val, int64_t nvec, int32_t k, double* out,
 hipError_t launch_merge(const int32_t* in_idx, const double* in_val, int64_t r, int32_t k,
                         int32_t* out_idx, double* out_val, hipStream_t stream);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream);
+hipError_t launch_rate_probe(int what, int64_t lanes, int32_t steps, uint64_t seed_mix,
+                             double* out, hipStream_t stream);
 }  // namespace gm
 
 namespace {
@@ -255,6 +257,15 @@ gm_status gm_wcard_est(const double* val, int64_t nvec, int32_t k, double* out,
   if (nvec == 0) return GM_OK;
   if (!val || !out) return GM_ERR_INVALID_ARG;
   return from_hip(gm::launch_wcard(val, nvec, k, out, stream));
+}
+
+gm_status gm_rate_probe(int32_t what, int64_t lanes, int32_t steps, uint64_t seed, double* out,
+                        hipStream_t stream) {
+  if ((what != 0 && what != 1) || lanes < 0 || steps < 1 || steps > GM_K_MAX)
+    return GM_ERR_INVALID_ARG;
+  if (lanes == 0) return GM_OK;
+  if (!out) return GM_ERR_INVALID_ARG;
+  return from_hip(gm::launch_rate_probe(what, lanes, steps, gm::mix(seed), out, stream));
 }
 
 gm_status gm_merge(const int32_t* in_idx, const double* in_val, int64_t r, int32_t k,

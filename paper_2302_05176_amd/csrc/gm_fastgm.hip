@@ -94,10 +94,10 @@ struct HeavyRec {
   int32_t ind;     // element index
   int32_t z;       // steps done
   int32_t nent;
-  uint32_t ent[16];
-  uint32_t pad[6];
+  uint32_t ent[kMapSlots];
+  uint32_t pad[(64 - (40 + 4 * kMapSlots) % 64) % 64 / 4];
 };
-static_assert(sizeof(HeavyRec) == 128, "heavy record layout");
+static_assert(sizeof(HeavyRec) % 64 == 0, "heavy record layout");
 
 struct PlanState {
   int count[kNumClasses];
@@ -155,6 +155,12 @@ enum : int {
   kStHeavyBatches = 6, // segment batches (one segment each) of that path
   kStPasses = 7,       // extra passes after an unfilled register
   kStResolves = 8,     // exact index resolutions after a contest
+  // wave clock cycles (s_memtime, summed over waves) spent in:
+  kStCycPrep = 9,      // register init, validation and sum
+  kStCycWalk = 10,     // first walk (probe and light path, segment path included)
+  kStCycSeg = 11,      // segment path (part of the walk)
+  kStCycExtra = 12,    // repeated walks (fallback and exact-index resolve)
+  kStCycOut = 13,      // completion checks and writeback
   kStCount = 16
 };
 
@@ -231,31 +237,46 @@ __device__ __forceinline__ double wave_max_register(const VecCtx& c) {
 
 // ---------------------------------------------------------------------------
 // Segment path.  An element whose displaced-position table fills up is walked
-// again from its first arrival by a segment of G lanes (G = 16: one DPP row,
-// four elements per wave; G = 64: the whole wave), G consecutive arrivals per
-// batch.  Its permutation is dense in LDS (one u16 per position, tagged with a
+// on by a segment of G lanes (G = 8: half a DPP row, eight elements per
+// wave; G = 16: one row, four elements; G = 64: the whole wave), G
+// consecutive arrivals per batch.  Its permutation is dense in LDS (one u16 per position, tagged with a
 // 3-bit generation so that a stale entry reads as the identity and a new
 // element needs no initialisation).
 
+// Value of lane l-1 of the segment in lane l; the segment's lane 0 receives
+// `first`.  G = 8 shifts whole rows (row_shr:1) and then gives the row's
+// lane 8 its own segment's `first`.
 template <int G>
 __device__ __forceinline__ double seg_shr1(double v, double first) {
-  constexpr int kCtrl = G == 16 ? 0x111 : 0x138;  // row_shr:1 / wave_shr:1
+  constexpr int kCtrl = G == 64 ? 0x138 : 0x111;  // wave_shr:1 / row_shr:1
   const uint64_t b = dbits(v), o = dbits(first);
   const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(o), static_cast<int>(b), kCtrl, 0xf,
                                              0xf, false);
   const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(o >> 32), static_cast<int>(b >> 32),
                                              kCtrl, 0xf, 0xf, false);
-  return bitsd((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo));
+  const double sh =
+      bitsd((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo));
+  if constexpr (G == 8) return (__lane_id() & 7u) == 0 ? first : sh;
+  return sh;
 }
 
-// Value of segment lane L, in every lane of the segment.
+// Value of segment lane L, in every lane of the segment (row_newbcast:L
+// broadcasts lane L of each row of 16; a G = 8 segment in the upper half of
+// a row takes row lane 8 + L).
 template <int G, int L>
 __device__ __forceinline__ uint32_t seg_bcast(uint32_t x) {
-  if constexpr (G == 16)
+  if constexpr (G == 16) {
     return static_cast<uint32_t>(
         __builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x150 + L, 0xf, 0xf, false));
-  else
+  } else if constexpr (G == 8) {
+    const uint32_t a = static_cast<uint32_t>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x150 + L, 0xf, 0xf, false));
+    const uint32_t b = static_cast<uint32_t>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x150 + 8 + L, 0xf, 0xf, false));
+    return (__lane_id() & 8u) ? b : a;
+  } else {
     return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), L));
+  }
 }
 
 template <int G, int L>
@@ -666,7 +687,9 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* 
         pend = false;
       }
       if (nheavy > 0) {
+        const uint64_t c0 = c.stats ? clock64() : 0;
         segment_walk<G>(c, hl, nheavy, pm, pm_stride, T);
+        if (c.stats && lane == 0) stat_add(c.stats, kStCycSeg, clock64() - c0);
         nheavy = 0;
         // the permutations overwrote the tables: clear them, restart stamps
         for (int s = 0; s < kMapSlots; ++s) mp[s * kWave] = 0u;
@@ -696,9 +719,11 @@ __device__ __forceinline__ double max_exp_quantile(int k) {
 
 __host__ __device__ constexpr int perm_stride(int k_max) { return ((k_max + 1 + 3) / 4) * 4; }
 
-// Lanes per segment of the segment path: 16 (four elements per wave) while
-// four dense permutations stay small, else the whole wave.
-__host__ __device__ constexpr int segment_lanes(int k_max) { return k_max <= 1024 ? 16 : 64; }
+// Lanes per segment of the segment path: 8 (eight elements per wave) or 16
+// (four) while that many dense permutations stay small, else the whole wave.
+__host__ __device__ constexpr int segment_lanes(int k_max) {
+  return k_max <= 256 ? 8 : (k_max <= 1024 ? 16 : 64);
+}
 
 __host__ __device__ constexpr size_t light_lds_bytes() {
   return queue_bytes() + static_cast<size_t>(kMapSlots) * kWave * 4;
@@ -765,6 +790,16 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   const int32_t span = out_span(p, v, d);
   const int64_t n64 = d.b - d.a;
   const bool bad0 = d.bad || n64 > 0x7FFFFFFF;
+  // optional per-phase cycle accounting (statistics mode only)
+  const bool timed = fa.stats != nullptr;
+  uint64_t cyc = timed ? clock64() : 0;
+  auto lap = [&](int slot) {
+    if (timed) {
+      const uint64_t now = clock64();
+      if (lane == 0) stat_add(fa.stats, slot, now - cyc);
+      cyc = now;
+    }
+  };
   if (tid == 0) {
     sh.bad = bad0 ? 1 : 0;
     sh.contest = 0;
@@ -822,6 +857,7 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   group_sync<GW>();
   double S = 0.0;
   for (int qq = 0; qq < GW; ++qq) S += sh.wsum[qq];
+  lap(kStCycPrep);
   if (sh.bad || !(S > 0.0)) {
     const bool bad = sh.bad != 0;
     for (int j = tid; j < span; j += kBlock) {
@@ -867,6 +903,7 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   for (int pass = 0;; ++pass) {
     walk_wave<G>(c, cursor, T, hl, pm, pm_stride, mp, stamp, q);
     group_sync<GW>();
+    lap(pass == 0 ? kStCycWalk : kStCycExtra);
     if (resolve) break;
     bool miss = false;
     for (int j = tid; j < d.k; j += kBlock) miss |= fullkey[j] == kInfBits;
@@ -922,6 +959,7 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
     }
   }
   group_sync<GW>();
+  lap(kStCycOut);
 }
 
 // Persistent kernel of one class: workgroups of W waves pull vector ids from
@@ -1415,8 +1453,10 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
       fa.lds_k = s.k_max < kclass_hi(kc) ? s.k_max : kclass_hi(kc);
       int waves = 1;
       class_shape(sc, fa.lds_k, small_waves, &waves, &fa.wave_lim);
-      e = segment_lanes(fa.lds_k) == 16 ? launch_class_w<16>(fa, waves, cus, stream)
-                                        : launch_class_w<64>(fa, waves, cus, stream);
+      const int g = segment_lanes(fa.lds_k);
+      e = g == 8 ? launch_class_w<8>(fa, waves, cus, stream)
+                 : (g == 16 ? launch_class_w<16>(fa, waves, cus, stream)
+                            : launch_class_w<64>(fa, waves, cus, stream));
       if (e != hipSuccess) return e;
     }
   }

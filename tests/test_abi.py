@@ -57,6 +57,10 @@ def test_host_side_argument_validation(lib):
     assert lib.gm_jaccard_est_pairs(fake, 1, 8, nul, fake, 1, fake, nul) == N.GM_ERR_INVALID_ARG
     assert lib.gm_merge(fake, fake, 0, 8, fake, fake, nul) == N.GM_ERR_INVALID_ARG
     assert lib.gm_get_data_errors(None, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_rate_probe(2, 64, 8, u, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_rate_probe(0, 64, 0, u, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_rate_probe(0, 64, 8, u, nul, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_rate_probe(1, 0, 8, u, nul, nul) == N.GM_OK
     # empty work is a no-op
     assert lib.gm_sketch(nul, nul, nul, 0, 8, u, nul, nul, nul) == N.GM_OK
     assert lib.gm_jaccard_est(nul, nul, 0, 8, nul, nul) == N.GM_OK
