@@ -65,7 +65,7 @@ constexpr int kMapSlots = 16;   // per-lane displaced-position table
 // walk is over), so that its dense permutations can reuse the LDS of the
 // light path's queue and tables.
 constexpr int kHeavyCapG = 512;
-constexpr int kQueueCap = 64;   // per-wave candidate queue (one probe pass)
+constexpr int kQueueCap = 128;  // per-wave candidate queue (probes run while it has room for 64)
 // Vectors are grouped by size class (up to kLimM entries, and big) and k
 // class (k <= 256, 1024, 2048, 4096) so that each persistent kernel sizes its
 // LDS for its own k range.  Class id = size_class * kKClasses + k_class; the
