@@ -711,11 +711,19 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* 
   }
 }
 
-// (1 - p) quantile of the maximum of k Exp(1) variables, p = 1e-4.
-__device__ __forceinline__ double max_exp_quantile(int k) {
-  const double p = 1e-4;
+// (1 - p) quantile of the maximum of k Exp(1) variables: a vector's final
+// y* exceeds x/S with probability p (Sec. 2.5).
+__device__ __forceinline__ double max_exp_quantile(int k, double p = 1e-4) {
   return -log(-expm1(log1p(-p) / static_cast<double>(k)));
 }
+
+// Miss probability of the first walk's threshold for vectors walked over all
+// their entries.  A miss (an empty register) costs one more walk with the
+// threshold doubled, past the 1e-4 quantile; a tighter first threshold saves
+// the arrivals between the two quantiles on every other vector, which
+// matters most for large k, where the registers fill late in the walk and
+// the running maximum cannot tighten the threshold before that.
+constexpr double kFirstMiss = 0.03;
 
 __host__ __device__ constexpr int perm_stride(int k_max) { return ((k_max + 1 + 3) / 4) * 4; }
 
@@ -898,7 +906,8 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   // register is empty; then, if two entries tied on a packed prefix, walk
   // once more to resolve the indices exactly.  One call site keeps a single
   // copy of the walk in the kernel.
-  double T = max_exp_quantile(d.k) * fa.t0_scale / S;
+  // big vectors keep the quantile their candidate lists were cut at
+  double T = max_exp_quantile(d.k, bi ? 1e-4 : kFirstMiss) * fa.t0_scale / S;
   bool resolve = false;
   for (int pass = 0;; ++pass) {
     walk_wave<G>(c, cursor, T, hl, pm, pm_stride, mp, stamp, q);
