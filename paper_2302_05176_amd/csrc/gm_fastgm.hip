@@ -38,15 +38,15 @@
 //  * Light path: lanes pop candidates and continue their walks from step 2,
 //    one arrival per lane per iteration.  The Fisher-Yates state of a walk is
 //    the set of displaced positions, kept per lane in a small open-addressing
-//    table in LDS (entries stamped with a per-lane element counter, so a new
+//    table in LDS (the lane tracks its occupied slots in a register mask, so a new
 //    element starts with an empty table for free).
-//  * Heavy path: an element whose table fills up is re-walked from its start
-//    by the whole wave: 64 consecutive arrivals are drawn in parallel, the
+//  * Segment path: an element expected to walk long, or whose table fills
+//    up, is listed with its walk state and continued later by a segment of
+//    8, 16 or 64 lanes: consecutive arrivals are drawn in parallel, the
 //    order-statistic prefix O_z = fma(E_z, c_z, O_{z-1}) is accumulated in
-//    its defined serial order by a chain of DPP lane shifts (lane z holds O_z
-//    after z steps), and the 64 Fisher-Yates swaps are resolved against a
-//    dense LDS permutation by a branch-free pass over the batch's earlier
-//    targets.
+//    its defined serial order by a chain of DPP lane shifts, and the swaps
+//    are resolved against a dense LDS permutation by a branch-free pass over
+//    the batch's earlier targets.
 //  * Exact indices on contest: walk again with the exact final y* and, for
 //    every arrival whose key equals its register's final key, atomic-min the
 //    element index into the register.
@@ -423,32 +423,52 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy,
   }
 }
 
-// Per-lane displaced-position table: entry = stamp:8 | (pos-1):12 | (val-1):12,
-// slot s of this lane at mp[s * kWave], home slot (pos-1) mod kMapSlots,
-// linear probing.  map_resolve continues a lookup of position p whose home
-// entry `e` was already read: returns the value at p (p if not displaced);
-// `slot` receives p's slot or the first free slot of its probe chain (-1 if
-// the table is full), `found` whether p was present.
-__device__ __forceinline__ uint32_t map_resolve(const lds_u32* mp, uint32_t stamp, uint32_t p,
-                                                uint32_t e, int& slot, bool& found) {
+// Per-lane displaced-position table: entry = (pos-1):12 | (val-1):12 in slot
+// s of this lane at mp[s * kWave], home slot (pos-1) mod kMapSlots, linear
+// probing.  The lane keeps in registers which slots hold entries of its
+// current element (`occ`, one bit per slot) and a 64-bit filter of the
+// positions entered (`bloom`, bit pos mod 64): most lookups miss, and a
+// filter miss needs no LDS read.  A new element starts with both zero.
+struct LaneMap {
+  uint32_t occ;
+  uint64_t bloom;
+};
+
+// Value at position p (p if not displaced); `slot` receives p's slot when
+// found, `found` whether p was present.
+__device__ __forceinline__ uint32_t map_find(const lds_u32* mp, const LaneMap& m, uint32_t p,
+                                             int& slot, bool& found) {
+  found = false;
+  slot = -1;
+  if (((m.bloom >> (p & 63u)) & 1ull) == 0) return p;
   const uint32_t key = p - 1;
   int s = static_cast<int>(key & (kMapSlots - 1));
-  found = false;
   for (int q = 0; q < kMapSlots; ++q) {
-    if ((e >> 24) != stamp) {
-      slot = s;
-      return p;
-    }
-    if (((e >> 12) & 0xFFFu) == key) {
+    if (((m.occ >> s) & 1u) == 0) return p;
+    const uint32_t e = mp[s * kWave];
+    if ((e >> 12) == key) {
       slot = s;
       found = true;
       return (e & 0xFFFu) + 1;
     }
     s = (s + 1) & (kMapSlots - 1);
-    e = mp[s * kWave];
   }
-  slot = -1;
   return p;
+}
+
+// First free slot at or after position p's home slot (-1: table full).
+__device__ __forceinline__ int map_free_slot(const LaneMap& m, uint32_t p) {
+  const uint32_t h = (p - 1) & (kMapSlots - 1);
+  const uint32_t fr = ~m.occ & ((1u << kMapSlots) - 1u);
+  const uint32_t rot = ((fr >> h) | (fr << (kMapSlots - h))) & ((1u << kMapSlots) - 1u);
+  if (rot == 0) return -1;
+  return static_cast<int>((h + static_cast<uint32_t>(__builtin_ctz(rot))) & (kMapSlots - 1));
+}
+
+__device__ __forceinline__ void map_put(lds_u32* mp, LaneMap& m, int slot, uint32_t p, uint32_t v) {
+  mp[slot * kWave] = ((p - 1) << 12) | (v - 1);
+  m.occ |= 1u << slot;
+  m.bloom |= 1ull << (p & 63u);
 }
 
 // Candidate queue of one wave: elements whose first arrival passed the
@@ -480,7 +500,7 @@ __host__ __device__ constexpr size_t queue_bytes() { return kQueueCap * (8 + 8 +
 // tables for its permutations; the tables are cleared afterwards.
 template <int G>
 __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* hl, lds_u16* pm,
-                          int pm_stride, lds_u32* mp, uint32_t& stamp, const Queue& q) {
+                          int pm_stride, lds_u32* mp, const Queue& q) {
   const int lane = __lane_id();
   const double c1 = 1.0 / static_cast<double>(c.k);
   bool have = false;
@@ -489,7 +509,9 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* 
   double r = 0.0, O = 0.0;
   uint64_t P = 0;
   int32_t z = 0;
-  int32_t entries = 0;
+  LaneMap lm;
+  lm.occ = 0;
+  lm.bloom = 0;
   int qhead = 0, qtail = 0;   // wave-uniform ring counters
   int nheavy = 0;             // wave-uniform heavy-list length
   int iter = 0;
@@ -597,17 +619,10 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* 
             have = true;
             z = 1;
             ++started;
-            stamp = stamp + 1;
-            if (stamp == 256u) {
-              for (int s = 0; s < kMapSlots; ++s) mp[s * kWave] = 0u;
-              stamp = 1u;
-            }
             // after step 1, position j1 holds value 1
-            entries = 0;
-            if (j1 != 1u) {
-              mp[((j1 - 1) & (kMapSlots - 1)) * kWave] = (stamp << 24) | ((j1 - 1) << 12);
-              entries = 1;
-            }
+            lm.occ = 0;
+            lm.bloom = 0;
+            if (j1 != 1u) map_put(mp, lm, static_cast<int>((j1 - 1) & (kMapSlots - 1)), j1, 1u);
           }
         }
       }
@@ -632,21 +647,17 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* 
         } else {
           ++kept;
           const int32_t j = randint(draw(P, kTagShuffle, static_cast<uint32_t>(z)), z, c.k);
-          // home slots of z and j read together, chains followed only on collision
-          const uint32_t ez = mp[((z - 1) & (kMapSlots - 1)) * kWave];
-          const uint32_t ej = mp[((j - 1) & (kMapSlots - 1)) * kWave];
           int zslot, jslot;
           bool zfound, jfound;
-          const uint32_t vz = map_resolve(mp, stamp, static_cast<uint32_t>(z), ez, zslot, zfound);
-          const uint32_t vj = map_resolve(mp, stamp, static_cast<uint32_t>(j), ej, jslot, jfound);
+          const uint32_t vz = map_find(mp, lm, static_cast<uint32_t>(z), zslot, zfound);
+          const uint32_t vj = map_find(mp, lm, static_cast<uint32_t>(j), jslot, jfound);
           if (j != z) {
-            if (jslot < 0 || (!jfound && entries >= c.map_load)) {
-              overflow = true;
-            } else {
-              mp[jslot * kWave] =
-                  (stamp << 24) | (static_cast<uint32_t>(j - 1) << 12) | (vz - 1);
-              entries += jfound ? 0 : 1;
+            // position j now holds the value position z held
+            if (!jfound) {
+              jslot = __popc(lm.occ) < c.map_load ? map_free_slot(lm, static_cast<uint32_t>(j)) : -1;
+              if (jslot < 0) overflow = true;
             }
+            if (!overflow) map_put(mp, lm, jslot, static_cast<uint32_t>(j), vz);
           }
           if (overflow) {
             have = false;
@@ -674,10 +685,8 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* 
       hr->ind = ind;
       hr->z = z - 1;
       int ne = 0;
-      for (int s2 = 0; s2 < kMapSlots; ++s2) {
-        const uint32_t me = mp[s2 * kWave];
-        if ((me >> 24) == stamp) hr->ent[ne++] = me & 0xFFFFFFu;
-      }
+      for (int s2 = 0; s2 < kMapSlots; ++s2)
+        if ((lm.occ >> s2) & 1u) hr->ent[ne++] = mp[s2 * kWave];
       hr->nent = ne;
     }
     nheavy += __popcll(om);
@@ -691,9 +700,6 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* 
         segment_walk<G>(c, hl, nheavy, pm, pm_stride, T);
         if (c.stats && lane == 0) stat_add(c.stats, kStCycSeg, clock64() - c0);
         nheavy = 0;
-        // the permutations overwrote the tables: clear them, restart stamps
-        for (int s = 0; s < kMapSlots; ++s) mp[s * kWave] = 0u;
-        stamp = 0u;
       }
       if (!more) break;
     }
@@ -788,7 +794,7 @@ __device__ __forceinline__ bool group_or(bool b) {
 template <int GW, int G>
 __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, FgShared& sh,
                               lds_u64* packed, lds_u64* fullkey, lds_u16* pm, int pm_stride,
-                              HeavyRec* hl, lds_u32* mp, uint32_t& stamp, const Queue& q) {
+                              HeavyRec* hl, lds_u32* mp, const Queue& q) {
   constexpr int kBlock = GW * kWave;
   const SketchArgs& p = fa.s;
   const int lane = threadIdx.x % kWave;
@@ -910,7 +916,7 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   double T = max_exp_quantile(d.k, bi ? 1e-4 : kFirstMiss) * fa.t0_scale / S;
   bool resolve = false;
   for (int pass = 0;; ++pass) {
-    walk_wave<G>(c, cursor, T, hl, pm, pm_stride, mp, stamp, q);
+    walk_wave<G>(c, cursor, T, hl, pm, pm_stride, mp, q);
     group_sync<GW>();
     lap(pass == 0 ? kStCycWalk : kStCycExtra);
     if (resolve) break;
@@ -1003,8 +1009,6 @@ void fastgm_class_kernel(FastArgs fa) {
   HeavyRec* hl = fa.heavy + (static_cast<int64_t>(blockIdx.x) * W + wave) * kHeavyCapG;
   const int lane = threadIdx.x % kWave;
   lds_u32* mp = mp_base + lane;
-  for (int s = 0; s < kMapSlots; ++s) mp[s * kWave] = 0u;
-  uint32_t stamp = 0;
 
   const PlanState* plan = fa.plan;
   const int count = plan->count[fa.cls];
@@ -1022,7 +1026,7 @@ void fastgm_class_kernel(FastArgs fa) {
     const BigInfo* bi =
         (fa.cls >= kBigFirst && fa.big) ? &fa.big[plan->offset[fa.cls] - plan->offset[kBigFirst] + t]
                                         : nullptr;
-    sketch_vector<W, G>(fa, v, bi, sh[0], regs, regs + k_max, pm, pm_stride, hl, mp, stamp, q);
+    sketch_vector<W, G>(fa, v, bi, sh[0], regs, regs + k_max, pm, pm_stride, hl, mp, q);
   }
   // one vector per wave from here on (wave 0 starts with the task in hand)
   lds_u64* wpacked = regs + 2 * k_max * wave;
@@ -1035,7 +1039,7 @@ void fastgm_class_kernel(FastArgs fa) {
     }
     if (mt >= count) break;
     sketch_vector<1, G>(fa, list[mt], nullptr, sh[wave], wpacked, wpacked + k_max, pm, pm_stride,
-                        hl, mp, stamp, q);
+                        hl, mp, q);
     mt = -1;
   }
 }
