@@ -48,11 +48,16 @@ ARRIVAL_SLOTS = 100
 # lexicographic min): 88 VALU instructions, 81 slots.
 PLAIN_KEY_SLOTS = 81
 HBM_PEAK = 8.0e12
-# The FastGM launch that takes most of a k <= 256 step: every vector of at
-# most 32768 entries (larger ones are prepared by grid-wide passes and walked
-# by another launch).
-DOMINANT = "fastgm_class_kernel<4, 16>"
+# The FastGM launch that takes most of a step drains every vector of at most
+# 32768 entries of the batch's k range (larger ones are prepared by grid-wide
+# passes and walked by another launch); the library names its timing entry
+# "fastgm_class_kernel<W, G> [class c]" with c the k range (k <= 256: 0,
+# <= 1024: 1, <= 2048: 2, else 3).
 SMALL_LIMIT = 32768
+
+
+def k_class(k: int) -> int:
+    return 0 if k <= 256 else (1 if k <= 1024 else (2 if k <= 2048 else 3))
 
 
 def harmonic(k: int) -> float:
@@ -248,7 +253,9 @@ def bench_batch(args):
     regs = args.nvec * k
     value = regs / (ms_step / 1e3)
     if args.form == "fastgm":
-        kern = DOMINANT
+        key = next(n for n in kt if n.startswith("fastgm_class_kernel")
+                   and n.endswith(f"[class {k_class(k)}]"))
+        kern = key.split(" [")[0]
         small = nplus <= SMALL_LIMIT
         units = float(small.sum() * k * harmonic(k) + nplus[small].sum())
         slots = ARRIVAL_SLOTS
@@ -260,9 +267,7 @@ def bench_batch(args):
         slots = PLAIN_KEY_SLOTS
         unit_name = "keys (k n+)"
         vec_bytes = 8.0 * nnz + 8.0 * (args.nvec + 1) + 12.0 * regs
-    # the library names each FastGM launch after its kernel and the class it
-    # drains; at k <= 256 the dominant kernel drains class 0 only
-    tot_ms, launches = kt.get(kern + " [class 0]" if args.form == "fastgm" else kern, (0.0, 0))
+    tot_ms, launches = kt.get(key if args.form == "fastgm" else kern, (0.0, 0))
     kern_s = tot_ms / launches / 1e3 if launches else ev_ms / 1e3
     achieved = units * slots / kern_s
     traffic = committed_traffic(kern, f"batch_k{k}_{args.form}")
