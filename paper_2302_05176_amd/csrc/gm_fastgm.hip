@@ -265,14 +265,15 @@ __device__ __forceinline__ double seg_shr1(double v, double first) {
 // a row takes row lane 8 + L).
 template <int G, int L>
 __device__ __forceinline__ uint32_t seg_bcast(uint32_t x) {
+  // row_newbcast writes every lane, so no "old" value is needed (bound_ctrl)
   if constexpr (G == 16) {
     return static_cast<uint32_t>(
-        __builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x150 + L, 0xf, 0xf, false));
+        __builtin_amdgcn_mov_dpp(static_cast<int>(x), 0x150 + L, 0xf, 0xf, true));
   } else if constexpr (G == 8) {
     const uint32_t a = static_cast<uint32_t>(
-        __builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x150 + L, 0xf, 0xf, false));
+        __builtin_amdgcn_mov_dpp(static_cast<int>(x), 0x150 + L, 0xf, 0xf, true));
     const uint32_t b = static_cast<uint32_t>(
-        __builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x150 + 8 + L, 0xf, 0xf, false));
+        __builtin_amdgcn_mov_dpp(static_cast<int>(x), 0x150 + 8 + L, 0xf, 0xf, true));
     return (__lane_id() & 8u) ? b : a;
   } else {
     return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), L));
