@@ -157,7 +157,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["batch", "single", "stream", "uneven", "serve", "rates"],
+    ap.add_argument("--workload", choices=["batch", "single", "stream", "stream_update", "uneven",
+                                           "serve", "rates"],
                     default="batch")
     ap.add_argument("--form", choices=["fastgm", "plain"], default="fastgm")
     ap.add_argument("--k", type=int, default=256)
@@ -388,6 +389,46 @@ def bench_stream(args):
                       "results": out}), flush=True)
 
 
+def bench_stream_update(args):
+    """Stream-FastGM through the update API: the 10^7-entry stream arrives in
+    ten chunks of 10^6 entries (in stream order), each merged into one stored
+    sketch; later chunks stop at the stored sketch's y* and get cheaper."""
+    import numpy as np
+    import torch
+
+    import paper_2302_05176_amd as gm
+    from paper_2302_05176_amd import workloads as W
+    dev = torch.device("cuda:0")
+    idx, w, off = W.stream(nplus=10_000_000)
+    n = int(off[-1])
+    out = {}
+    for k in (1024, 4096):
+        chunks = []
+        for c in range(10):
+            a, b = c * n // 10, (c + 1) * n // 10
+            chunks.append((torch.from_numpy(idx[a:b]).to(dev), torch.from_numpy(w[a:b]).to(dev),
+                           torch.tensor([0, b - a], dtype=torch.int64, device=dev)))
+        ms_chunks = []
+        for rep in range(2):          # the first pass warms up
+            si, sv = gm.empty_sketches(1, k, dev)
+            ms_chunks = []
+            for ti, tw, to in chunks:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                gm.sketch_update(ti, tw, to, k, args.seed, si, sv)
+                e1.record()
+                torch.cuda.synchronize()
+                ms_chunks.append(e0.elapsed_time(e1))
+        ti, tw, to = (torch.from_numpy(a).to(dev) for a in (idx, w, off))
+        whole_i, whole_v = gm.sketch(ti, tw, to, k, args.seed)
+        same = bool(torch.equal(whole_i, si) and torch.equal(whole_v, sv))
+        out[f"k{k}"] = {"chunk_ms": [round(x, 4) for x in ms_chunks], "total_ms": sum(ms_chunks),
+                        "entries_per_s": n / (sum(ms_chunks) / 1e3), "equals_whole_sketch": same}
+    print(json.dumps({"workload": "stream update: one 10^7-entry vector (half Uniform(0,1], half "
+                                  "1+Pareto(1.5)) in ten 10^6-entry chunks", "results": out}),
+          flush=True)
+
+
 def bench_uneven(args):
     import numpy as np
     import torch
@@ -485,7 +526,8 @@ def main():
     import torch
     torch.cuda.set_device(0)
     {"batch": bench_batch, "single": bench_single, "stream": bench_stream,
-     "uneven": bench_uneven, "serve": bench_serve, "rates": bench_rates}[args.workload](args)
+     "uneven": bench_uneven, "serve": bench_serve, "rates": bench_rates,
+     "stream_update": bench_stream_update}[args.workload](args)
 
 
 if __name__ == "__main__":

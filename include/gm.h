@@ -94,6 +94,24 @@ gm_status gm_sketch(const int32_t *indices, const float *weights, const int64_t 
                     int32_t *out_idx, double *out_val, hipStream_t stream);
 
 /*
+ * gm_sketch_update -- streaming update (Sec. 3, Algorithm 2; mergeability,
+ * Sec. 2.3): sk_idx/sk_val (device, row-major [nvec][k], caller-owned) hold
+ * the FastGM-form sketches, under the same k and seed, of the entries seen
+ * so far (an all-empty row, (-1, +inf), stands for none); vector v's new
+ * entries [offsets[v], offsets[v+1]) are merged in place, so that the row
+ * becomes the sketch of the union of old and new entries -- bit for bit the
+ * result of gm_sketch over that union.  Each vector's walk stops at its
+ * stored sketch's largest register (an arrival above it cannot change the
+ * result), so updates get cheaper as a stream goes on.  Repeated entries
+ * (same index and weight) change nothing.  Data errors poison the row
+ * (-2, NaN); a poisoned row stays poisoned; a vector with no positive entry
+ * leaves its row unchanged.  Argument errors as for gm_sketch.
+ */
+gm_status gm_sketch_update(const int32_t *indices, const float *weights, const int64_t *offsets,
+                           int64_t nvec, int32_t k, uint64_t seed, int32_t *sk_idx, double *sk_val,
+                           hipStream_t stream);
+
+/*
  * gm_sketch_plain -- plain form of Eq. (1)/(2): every (entry, register) key
  * is drawn and the minimum kept; O(k n+) per vector.  Same arguments and
  * layout as gm_sketch.  Register j of a k-register plain sketch equals

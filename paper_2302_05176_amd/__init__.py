@@ -76,6 +76,29 @@ def sketch(indices, weights, offsets, k: int, seed: int, form: str = "fastgm",
     return out_idx, out_val
 
 
+def empty_sketches(nvec: int, k: int, device=None):
+    """Rows of empty registers (-1, +inf): the sketch of no entries."""
+    torch = _torch()
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    return (torch.full((nvec, k), -1, dtype=torch.int32, device=device),
+            torch.full((nvec, k), float("inf"), dtype=torch.float64, device=device))
+
+
+def sketch_update(indices, weights, offsets, k: int, seed: int, sk_idx, sk_val, stream=None):
+    """Merge each row's new entries into its stored FastGM sketch in place
+    (gm_sketch_update); sk_idx/sk_val are int32/fp64 [nvec, k] device tensors."""
+    torch = _torch()
+    L = _native.load()
+    nvec = offsets.numel() - 1
+    st = L.gm_sketch_update(_dev(indices, torch.int32, "indices"),
+                            _dev(weights, torch.float32, "weights"),
+                            _dev(offsets, torch.int64, "offsets"), nvec, int(k),
+                            ctypes.c_uint64(seed), _dev(sk_idx, torch.int32, "sk_idx"),
+                            _dev(sk_val, torch.float64, "sk_val"), _stream(stream))
+    _native.check(st, "gm_sketch_update")
+    return sk_idx, sk_val
+
+
 def sketch_batched(indices, weights, offsets, k_per_vec, out_offsets, k_max: int, seed: int,
                    form: str = "fastgm", out_idx=None, out_val=None, stream=None):
     """Vectors with individual k; registers of vector v fill

@@ -59,6 +59,7 @@ def load() -> ctypes.CDLL:
     st = ctypes.c_int
     L.gm_sketch.argtypes = [p, p, p, i64, i32, u64, p, p, p]
     L.gm_sketch_plain.argtypes = [p, p, p, i64, i32, u64, p, p, p]
+    L.gm_sketch_update.argtypes = [p, p, p, i64, i32, u64, p, p, p]
     L.gm_sketch_batched.argtypes = [p, p, p, i64, p, p, i32, u64, ctypes.c_int, p, p, p]
     L.gm_jaccard_est.argtypes = [p, p, i64, i32, p, p]
     L.gm_jaccard_est_pairs.argtypes = [p, i64, i32, p, p, i64, p, p]

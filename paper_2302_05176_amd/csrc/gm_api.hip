@@ -15,7 +15,7 @@ hipError_t launch_plain(const SketchArgs& p, hipStream_t stream);
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
                          int republish, double seg_rest, int small_waves, int32_t* list,
                          void* plan, void* big, int32_t* pool, int64_t pool_cap,
-                         void* heavy, int64_t heavy_waves, int cus,
+                         void* heavy, int64_t heavy_waves, int update, int cus,
                          unsigned long long* stats, hipStream_t stream);
 size_t plan_state_bytes();
 int64_t heavy_list_bytes();
@@ -160,7 +160,8 @@ gm_status plan_workspace(DeviceState* st, hipStream_t stream, int64_t nvec, Plan
 gm_status sketch_common(const int32_t* indices, const float* weights, const int64_t* offsets,
                         int64_t nvec, int32_t k_uniform, const int32_t* kvec,
                         const int64_t* outoff, int32_t k_max, uint64_t seed, gm_form form,
-                        int32_t* out_idx, double* out_val, hipStream_t stream) {
+                        int32_t* out_idx, double* out_val, hipStream_t stream,
+                        int update = 0) {
   if (nvec < 0 || k_max < 1 || k_max > GM_K_MAX) return GM_ERR_INVALID_ARG;
   if (form != GM_FORM_FASTGM && form != GM_FORM_PLAIN) return GM_ERR_INVALID_ARG;
   if (nvec == 0) return GM_OK;
@@ -188,8 +189,8 @@ gm_status sketch_common(const int32_t* indices, const float* weights, const int6
   if (s != GM_OK) return s;
   return from_hip(gm::launch_fastgm(a, g_pos_bits, g_t0_scale, g_map_load, g_republish,
                                     g_seg_rest, g_small_waves, ws->list, ws->plan, ws->big,
-                                    ws->pool, kPoolCap, ws->heavy, ws->heavy_waves, st->cus,
-                                    g_stats ? st->stats : nullptr, stream));
+                                    ws->pool, kPoolCap, ws->heavy, ws->heavy_waves, update,
+                                    st->cus, g_stats ? st->stats : nullptr, stream));
 }
 
 }  // namespace
@@ -202,6 +203,14 @@ gm_status gm_sketch(const int32_t* indices, const float* weights, const int64_t*
   if (k < 1 || k > GM_K_MAX) return GM_ERR_INVALID_ARG;
   return sketch_common(indices, weights, offsets, nvec, k, nullptr, nullptr, k, seed,
                        GM_FORM_FASTGM, out_idx, out_val, stream);
+}
+
+gm_status gm_sketch_update(const int32_t* indices, const float* weights, const int64_t* offsets,
+                           int64_t nvec, int32_t k, uint64_t seed, int32_t* sk_idx, double* sk_val,
+                           hipStream_t stream) {
+  if (k < 1 || k > GM_K_MAX) return GM_ERR_INVALID_ARG;
+  return sketch_common(indices, weights, offsets, nvec, k, nullptr, nullptr, k, seed,
+                       GM_FORM_FASTGM, sk_idx, sk_val, stream, 1);
 }
 
 gm_status gm_sketch_plain(const int32_t* indices, const float* weights, const int64_t* offsets,

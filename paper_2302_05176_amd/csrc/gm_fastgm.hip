@@ -140,6 +140,7 @@ struct FastArgs {
   int32_t lds_k;        // register-array size this launch's LDS is laid out for
   unsigned long long* stats;  // optional counters (nullptr: off)
   HeavyRec* heavy;      // kHeavyCapG records per resident wave
+  int32_t update;       // 1: merge into the sketches already in out_idx/out_val
   int64_t wave_lim;     // vectors of at most this many entries: one wave each (0: none)
   int64_t heavy_waves;  // waves the heavy buffer has room for
 };
@@ -874,14 +875,43 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   for (int qq = 0; qq < GW; ++qq) S += sh.wsum[qq];
   lap(kStCycPrep);
   if (sh.bad || !(S > 0.0)) {
+    // an update with no positive entry leaves the stored sketch as it is
     const bool bad = sh.bad != 0;
-    for (int j = tid; j < span; j += kBlock) {
-      p.out_idx[d.o + j] = bad ? kIdxPoison : kIdxEmpty;
-      p.out_val[d.o + j] = bitsd(bad ? kNanBits : kInfBits);
+    if (bad || !fa.update) {
+      for (int j = tid; j < span; j += kBlock) {
+        p.out_idx[d.o + j] = bad ? kIdxPoison : kIdxEmpty;
+        p.out_val[d.o + j] = bitsd(bad ? kNanBits : kInfBits);
+      }
     }
     if (bad && tid == 0) atomicAdd(p.err, 1ull);
     group_sync<GW>();
     return;
+  }
+  // Update: the stored sketch is the sketch of the entries seen so far, so
+  // an arrival above its largest register cannot change the merged result
+  // (lexicographic minimum over the union, Sec. 2.3): its y* caps the walk.
+  double cap = bitsd(kInfBits);
+  if (fa.update) {
+    unsigned long long m = 0;
+    bool poisoned = false, empty = false;
+    for (int j = tid; j < d.k; j += kBlock) {
+      const int32_t si = p.out_idx[d.o + j];
+      if (si == kIdxPoison)
+        poisoned = true;
+      else if (si < 0)
+        empty = true;
+      else
+        m = dbits(p.out_val[d.o + j]) > m ? dbits(p.out_val[d.o + j]) : m;
+    }
+    m = wave_max_u64(m);
+    if (lane == 0) sh.wmax[wave] = m;
+    const bool any_poison = group_or<GW>(poisoned);  // also orders the wmax writes
+    const bool any_empty = group_or<GW>(empty);
+    if (any_poison) return;  // a poisoned sketch stays poisoned
+    unsigned long long ms = 0;
+    for (int qq = 0; qq < GW; ++qq) ms = sh.wmax[qq] > ms ? sh.wmax[qq] : ms;
+    if (!any_empty) cap = bitsd(ms);
+    group_sync<GW>();
   }
 
   VecCtx c;
@@ -914,7 +944,7 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   // once more to resolve the indices exactly.  One call site keeps a single
   // copy of the walk in the kernel.
   // big vectors keep the quantile their candidate lists were cut at
-  double T = max_exp_quantile(d.k, bi ? 1e-4 : kFirstMiss) * fa.t0_scale / S;
+  double T = fmin(max_exp_quantile(d.k, bi ? 1e-4 : kFirstMiss) * fa.t0_scale / S, cap);
   bool resolve = false;
   for (int pass = 0;; ++pass) {
     walk_wave<G>(c, cursor, T, hl, pm, pm_stride, mp, q);
@@ -923,9 +953,10 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
     if (resolve) break;
     bool miss = false;
     for (int j = tid; j < d.k; j += kBlock) miss |= fullkey[j] == kInfBits;
-    if (group_or<GW>(miss)) {
+    // (under an update's cap, a register left empty keeps its stored value)
+    if (group_or<GW>(miss) && T < cap) {
       if (tid == 0) stat_add(fa.stats, kStPasses, 1);
-      T = pass >= 8 ? bitsd(kInfBits) : T * 2.0;
+      T = fmin(pass >= 8 ? bitsd(kInfBits) : T * 2.0, cap);
       // above T0 the candidate list no longer covers every element
       c.gather = nullptr;
       c.n = static_cast<int32_t>(n64);
@@ -939,7 +970,8 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
     resolve = true;
     if (tid == 0) stat_add(fa.stats, kStResolves, 1);
     unsigned long long m = 0;
-    for (int j = tid; j < d.k; j += kBlock) m = fullkey[j] > m ? fullkey[j] : m;
+    for (int j = tid; j < d.k; j += kBlock)
+      if (fullkey[j] != kInfBits) m = fullkey[j] > m ? fullkey[j] : m;
     m = wave_max_u64(m);
     if (lane == 0) sh.wmax[wave] = m;
     group_sync<GW>();
@@ -961,16 +993,28 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
     for (int u = 0; u < kU; ++u) {
       const int j = j0 + u * kBlock;
       if (j < d.k) {
+        // (a register an update's cap left empty has no winner to look up)
         const unsigned long long pk = packed[j];
-        oi[u] = resolve ? static_cast<int32_t>(pk) : c.idx[pk & pmask];
+        oi[u] = resolve ? static_cast<int32_t>(pk)
+                        : (fullkey[j] != kInfBits ? c.idx[pk & pmask] : kIdxEmpty);
       }
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int j = j0 + u * kBlock;
       if (j < d.k) {
-        p.out_idx[d.o + j] = oi[u];
-        p.out_val[d.o + j] = bitsd(fullkey[j]);
+        const unsigned long long fk = fullkey[j];
+        bool take = true;
+        if (fa.update) {
+          // lexicographic (value, index) minimum with the stored register
+          const int32_t si = p.out_idx[d.o + j];
+          const unsigned long long sv = dbits(p.out_val[d.o + j]);
+          take = fk != kInfBits && (si < 0 || fk < sv || (fk == sv && oi[u] < si));
+        }
+        if (take) {
+          p.out_idx[d.o + j] = oi[u];
+          p.out_val[d.o + j] = bitsd(fk);
+        }
       }
     }
   }
@@ -1220,7 +1264,30 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
     const VecDesc d = vec_desc(p, list2[b]);
     BigInfo* bi = &fa.big[b];
     if (d.bad || bi->bad || !(bi->S > 0.0) || bi->cand_cap <= 0) continue;
-    const double T0 = max_exp_quantile(d.k) * fa.t0_scale / bi->S;
+    double T0 = max_exp_quantile(d.k) * fa.t0_scale / bi->S;
+    if (fa.update) {
+      // an update's walk stops at the stored sketch's largest register
+      __shared__ unsigned long long smax[kBigBlock / kWave];
+      __shared__ int sempty;
+      if (tid == 0) sempty = 0;
+      __syncthreads();
+      unsigned long long m = 0;
+      bool empty = false;
+      for (int j = tid; j < d.k; j += kBigBlock) {
+        if (p.out_idx[d.o + j] < 0)
+          empty = true;
+        else
+          m = dbits(p.out_val[d.o + j]) > m ? dbits(p.out_val[d.o + j]) : m;
+      }
+      m = wave_max_u64(m);
+      if (lane == 0) smax[tid / kWave] = m;
+      if (empty) sempty = 1;
+      __syncthreads();
+      unsigned long long ms = 0;
+      for (int qq = 0; qq < kBigBlock / kWave; ++qq) ms = smax[qq] > ms ? smax[qq] : ms;
+      if (!sempty) T0 = fmin(T0, bitsd(ms));
+      __syncthreads();
+    }
     const double c1 = 1.0 / static_cast<double>(d.k);
     const int64_t e0 = d.a + (t - bi->chunk_base) * kBigChunk;
     const int64_t e1 = e0 + kBigChunk < d.b ? e0 + kBigChunk : d.b;
@@ -1425,9 +1492,10 @@ constexpr int64_t kLimM = 32768;
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
                          int republish, double seg_rest, int small_waves, int32_t* list,
                          void* plan, void* big, int32_t* pool, int64_t pool_cap,
-                         void* heavy, int64_t heavy_waves, int cus,
+                         void* heavy, int64_t heavy_waves, int update, int cus,
                          unsigned long long* stats, hipStream_t stream) {
   FastArgs fa;
+  fa.update = update;
   fa.heavy = static_cast<HeavyRec*>(heavy);
   fa.heavy_waves = heavy_waves;
   fa.big = static_cast<BigInfo*>(big);

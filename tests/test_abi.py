@@ -26,7 +26,8 @@ def declared_symbols():
 
 def test_header_declares_expected_entry_points():
     syms = declared_symbols()
-    for s in ("gm_sketch", "gm_sketch_plain", "gm_sketch_batched", "gm_jaccard_est",
+    for s in ("gm_sketch", "gm_sketch_plain", "gm_sketch_batched", "gm_sketch_update",
+              "gm_jaccard_est",
               "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_get_data_errors",
               "gm_release"):
         assert s in syms
@@ -48,6 +49,9 @@ def test_host_side_argument_validation(lib):
     assert lib.gm_sketch(fake, fake, fake, 1, 4097, u, fake, fake, nul) == N.GM_ERR_INVALID_ARG
     assert lib.gm_sketch(nul, fake, fake, 1, 8, u, fake, fake, nul) == N.GM_ERR_INVALID_ARG
     assert lib.gm_sketch_plain(fake, fake, fake, 1, 8, u, nul, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_sketch_update(fake, fake, fake, 1, 0, u, fake, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_sketch_update(fake, fake, fake, 1, 8, u, fake, nul, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_sketch_update(nul, nul, nul, 0, 8, u, nul, nul, nul) == N.GM_OK
     assert lib.gm_sketch_batched(fake, fake, fake, 1, nul, fake, 8, u, 0, fake, fake,
                                  nul) == N.GM_ERR_INVALID_ARG
     assert lib.gm_sketch_batched(fake, fake, fake, 1, fake, fake, 8, u, 7, fake, fake,
