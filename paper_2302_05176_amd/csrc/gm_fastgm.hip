@@ -50,11 +50,13 @@
 //  * Exact indices on contest: walk again with the exact final y* and, for
 //    every arrival whose key equals its register's final key, atomic-min the
 //    element index into the register.
+#include <cstddef>
 #include <cstdio>
 #include <string>
 #include <utility>
 #include <vector>
 
+#include "gm.h"
 #include "gm_common.h"
 
 namespace gm {
@@ -85,7 +87,8 @@ constexpr int kPlanBins = 32;   // size sub-bins per class (log2 of n)
 // An element handed to the segment path, with the state of its walk so far:
 // after z steps the order statistic is O and the displaced positions are the
 // nent entries (pos-1) << 12 | (value-1); the segment path continues from
-// step z + 1.
+// step z + 1.  32 dwords: the fields in dwords 0-9, the entries in 16-31, so
+// that the lanes of a segment load a record together, a slice each.
 struct HeavyRec {
   uint64_t P;      // hash prefix
   double r;        // 1 / v
@@ -94,10 +97,10 @@ struct HeavyRec {
   int32_t ind;     // element index
   int32_t z;       // steps done
   int32_t nent;
+  uint32_t pad[6];
   uint32_t ent[kMapSlots];
-  uint32_t pad[(64 - (40 + 4 * kMapSlots) % 64) % 64 / 4];
 };
-static_assert(sizeof(HeavyRec) % 64 == 0, "heavy record layout");
+static_assert(sizeof(HeavyRec) == 128 && offsetof(HeavyRec, ent) == 64, "heavy record layout");
 
 struct PlanState {
   int count[kNumClasses];
@@ -237,6 +240,22 @@ __device__ __forceinline__ double wave_max_register(const VecCtx& c) {
 }
 
 // ---------------------------------------------------------------------------
+// c_m = 1/m for m = 1..GM_K_MAX (the step weight 1/(k-z+1) of Eq. 7-8),
+// rounded by the compiler's IEEE division, i.e. to the same value the
+// device's division gives.  Read from global memory (L1/L2-resident, 32 KB)
+// instead of a division sequence per arrival.
+struct RecipTab {
+  double v[GM_K_MAX + 1];
+};
+constexpr RecipTab make_recip_tab() {
+  RecipTab t{};
+  for (int m = 1; m <= GM_K_MAX; ++m) t.v[m] = 1.0 / static_cast<double>(m);
+  return t;
+}
+__device__ constexpr RecipTab kRecip = make_recip_tab();
+
+__device__ __forceinline__ double recip_step(int m) { return kRecip.v[m]; }
+
 // Segment path.  An element whose displaced-position table fills up is walked
 // on by a segment of G lanes (G = 8: half a DPP row, eight elements per
 // wave; G = 16: one row, four elements; G = 64: the whole wave), G
@@ -244,20 +263,29 @@ __device__ __forceinline__ double wave_max_register(const VecCtx& c) {
 // 3-bit generation so that a stale entry reads as the identity and a new
 // element needs no initialisation).
 
-// Value of lane l-1 of the segment in lane l; the segment's lane 0 receives
-// `first`.  G = 8 shifts whole rows (row_shr:1) and then gives the row's
-// lane 8 its own segment's `first`.
+// Bit 0 of every G-lane segment of the wave.
 template <int G>
-__device__ __forceinline__ double seg_shr1(double v, double first) {
+__host__ __device__ constexpr uint64_t seg_first_lanes() {
+  uint64_t m = 0;
+  for (int i = 0; i < kWave; i += G) m |= 1ull << i;
+  return m;
+}
+
+// Value of lane l-1 of the segment in lane l; the segment's lane 0 keeps its
+// value of `prev` (the DPP's old operand, so that no copy is needed when
+// `prev` is the previous shift).  G = 8 shifts whole rows (row_shr:1) and
+// keeps the row's lane 8 by a select.
+template <int G>
+__device__ __forceinline__ double seg_shr1(double v, double prev) {
   constexpr int kCtrl = G == 64 ? 0x138 : 0x111;  // wave_shr:1 / row_shr:1
-  const uint64_t b = dbits(v), o = dbits(first);
+  const uint64_t b = dbits(v), o = dbits(prev);
   const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(o), static_cast<int>(b), kCtrl, 0xf,
                                              0xf, false);
   const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(o >> 32), static_cast<int>(b >> 32),
                                              kCtrl, 0xf, 0xf, false);
   const double sh =
       bitsd((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo));
-  if constexpr (G == 8) return (__lane_id() & 7u) == 0 ? first : sh;
+  if constexpr (G == 8) return __builtin_amdgcn_inverse_ballot_w64(seg_first_lanes<8>()) ? prev : sh;
   return sh;
 }
 
@@ -289,30 +317,70 @@ __device__ __forceinline__ double seg_bcast_f64(double v) {
   return bitsd((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
-// Swap step L of a batch: lanes after L see what step L moved (the value it
-// displaced from position z_L now sits at j_L); lanes before L whose target
-// is j_L lose their write.
+// Swap step L of a batch.  Lanes after L whose target is j_L read what step
+// L moved there (the value it displaced from position z_L); a lane whose own
+// position is j_L holds that value from then on; lanes before L with the
+// same target lose their write.  The lane-order conditions are wave masks
+// (`after`: lanes past L in their segment; `before`: lanes before it).
+// Lanes past the segment's stop carry distinct negative targets, which match
+// nothing.
 template <int G, int L>
-__device__ __forceinline__ void fy_step(int li, int f, int32_t j, int32_t z, uint32_t& cval,
-                                        uint32_t& disp, bool& killed) {
+__device__ __forceinline__ void fy_step(int32_t j, int32_t z, uint32_t& cval, uint32_t& disp,
+                                        uint64_t& after, uint64_t& before, uint64_t& killm) {
   const uint32_t dl = seg_bcast<G, L>(disp);
   const int32_t jl = static_cast<int32_t>(seg_bcast<G, L>(static_cast<uint32_t>(j)));
-  const bool act = L < f;
-  cval = (act && li > L && j == jl) ? dl : cval;
-  disp = (act && li > L && z == jl) ? dl : disp;
-  killed = killed || (act && li < L && j == jl);
+  const uint64_t eqj = __ballot(j == jl);
+  const uint64_t eqz = __ballot(z == jl);
+  cval = __builtin_amdgcn_inverse_ballot_w64(eqj & after) ? dl : cval;
+  disp = __builtin_amdgcn_inverse_ballot_w64(eqz) ? dl : disp;
+  killm |= eqj & before;
+  before = (before << 1) | seg_first_lanes<G>();
+  after = (after << 1) & after;
 }
 
 template <int G, int... Ls>
-__device__ __forceinline__ void fy_batch(std::integer_sequence<int, Ls...>, int li, int f,
-                                         int32_t j, int32_t z, uint32_t& cval, uint32_t& disp,
-                                         bool& killed) {
-  (fy_step<G, Ls>(li, f, j, z, cval, disp, killed), ...);
+__device__ __forceinline__ bool fy_batch(std::integer_sequence<int, Ls...>, int32_t j, int32_t z,
+                                         uint32_t& cval, uint32_t& disp) {
+  uint64_t after = ~seg_first_lanes<G>(), before = 0, killm = 0;
+  // computed step by step with two scalar operations each: folded to
+  // constants, the masks of all steps would be hoisted and held in scalar
+  // registers across the whole walk
+  asm volatile("" : "+s"(after), "+s"(before));
+  (fy_step<G, Ls>(j, z, cval, disp, after, before, killm), ...);
+  return __builtin_amdgcn_inverse_ballot_w64(killm);
+}
+
+// Dwords of a heavy record that one lane of a G-lane segment holds when the
+// segment loads the record together (a 64-lane segment: lanes 0-31, one each).
+template <int G>
+constexpr int rec_dwords() { return G >= 32 ? 1 : 32 / G; }
+
+template <int G>
+__device__ __forceinline__ void rec_load(const HeavyRec* hr, int li, uint32_t (&d)[rec_dwords<G>()]) {
+  constexpr int D = rec_dwords<G>();
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(hr) + li * D;
+  if constexpr (D == 4) {
+    const uint4 v = *reinterpret_cast<const uint4*>(src);
+    d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+  } else if constexpr (D == 2) {
+    const uint2 v = *reinterpret_cast<const uint2*>(src);
+    d[0] = v.x; d[1] = v.y;
+  } else {
+    d[0] = li < 32 ? src[0] : 0u;
+  }
+}
+
+// Dword I of the segment's record, in every lane of the segment.
+template <int G, int I>
+__device__ __forceinline__ uint32_t rec_field(const uint32_t (&d)[rec_dwords<G>()]) {
+  constexpr int D = rec_dwords<G>();
+  return seg_bcast<G, I / D>(d[I % D]);
 }
 
 template <int G>
 __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy, lds_u16* pm_all,
                              int pm_stride, double& T) {
+  constexpr int D = rec_dwords<G>();
   const int lane = __lane_id();
   const int row = lane / G;
   const int li = lane % G;
@@ -334,37 +402,55 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy,
   double r = 0.0, O = 0.0;
   uint64_t P = 0;
   int z0 = 1;
-  int next = 0;
   int batches = 0, elems = 0;  // per segment (statistics only)
   int round = 0;               // wave-uniform batch counter
+  // Each segment holds the record of its next element, loaded when it
+  // starts the previous one, so that its load latency is hidden.
+  const uint64_t below = row == 0 ? 0ull : (~0ull >> (64 - row * G));
+  uint32_t rec[D];
+  bool have_rec = false;
+  int next = 0;                // wave-uniform: records handed out
+  auto fetch = [&]() {
+    const uint64_t need = __ballot(!have_rec && li == 0);
+    if (need && next < nheavy) {
+      const int slot = next + __popcll(need & below);
+      if (!have_rec && slot < nheavy) {
+        rec_load<G>(heavy + slot, li, rec);
+        have_rec = true;
+      }
+      const int ni = __popcll(need);
+      next += ni < nheavy - next ? ni : nheavy - next;
+    }
+  };
+  fetch();
   while (true) {
-    // idle segments take the next listed elements
-    const uint64_t idle = __ballot(!active && li == 0);
-    if (idle && next < nheavy) {
-      const uint64_t below = row == 0 ? 0ull : (~0ull >> (64 - row * G));
-      const int slot = next + __popcll(idle & below);
-      if (!active && slot < nheavy) {
-        const HeavyRec* hr = heavy + slot;
-        hpos = static_cast<uint32_t>(hr->pos);
-        ind = hr->ind;
-        r = hr->r;
-        P = hr->P;
-        O = hr->O;
-        z0 = hr->z + 1;
-        const int nent = hr->nent;
+    // idle segments start their fetched element and fetch the one after it
+    if (__ballot(!active && have_rec)) {
+      if (!active && have_rec) {
+        P = (static_cast<uint64_t>(rec_field<G, 1>(rec)) << 32) | rec_field<G, 0>(rec);
+        r = bitsd((static_cast<uint64_t>(rec_field<G, 3>(rec)) << 32) | rec_field<G, 2>(rec));
+        O = bitsd((static_cast<uint64_t>(rec_field<G, 5>(rec)) << 32) | rec_field<G, 4>(rec));
+        hpos = rec_field<G, 6>(rec);
+        ind = static_cast<int32_t>(rec_field<G, 7>(rec));
+        z0 = static_cast<int>(rec_field<G, 8>(rec)) + 1;
+        const int nent = static_cast<int>(rec_field<G, 9>(rec));
         active = true;
+        have_rec = false;
         ++elems;
         hgen = hgen == 7u ? 1u : hgen + 1u;
         if (hgen == 1u)
           for (int q = li; q <= k; q += G) pm[q] = 0;
-        // the displaced positions of the walk so far
-        for (int q = li; q < nent; q += G) {
-          const uint32_t e = hr->ent[q];
-          pm[(e >> 12) + 1] = static_cast<uint16_t>((hgen << 13) | ((e & 0xFFFu) + 1));
+        // the displaced positions of the walk so far (dwords 16 + e)
+#pragma unroll
+        for (int cc = 0; cc < D; ++cc) {
+          const int e = li * D + cc - 16;
+          if (e >= 0 && e < nent) {
+            const uint32_t en = rec[cc];
+            pm[(en >> 12) + 1] = static_cast<uint16_t>((hgen << 13) | ((en & 0xFFFu) + 1));
+          }
         }
       }
-      const int ni = __popcll(idle);
-      next += ni < nheavy - next ? ni : nheavy - next;
+      fetch();
     }
     if (__ballot(active) == 0) break;
     const int z = z0 + li;
@@ -373,14 +459,18 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy,
     int32_t j = z;
     if (valid) {
       E = exp1(draw(P, kTagArrival, static_cast<uint32_t>(z)));
-      cz = 1.0 / static_cast<double>(k - z + 1);
+      cz = recip_step(k - z + 1);
       j = randint(draw(P, kTagShuffle, static_cast<uint32_t>(z)), z, k);
     }
     // O_z = fma(E_z, c_z, O_{z-1}) in its defined order: after step i lanes
     // 0..i of the segment hold their final value.
     double Ol = fma(E, cz, O);
+    double prev = O;
 #pragma unroll
-    for (int i = 1; i < G; ++i) Ol = fma(E, cz, seg_shr1<G>(Ol, O));
+    for (int i = 1; i < G; ++i) {
+      prev = seg_shr1<G>(Ol, prev);
+      Ol = fma(E, cz, prev);
+    }
     const double t = Ol * r;
     const uint64_t stopm = __ballot(valid && t > T);
     const uint64_t validm = __ballot(valid);
@@ -394,13 +484,9 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy,
       cval = (ej >> 13) == hgen ? (ej & 0x1FFFu) : static_cast<uint32_t>(j);
       disp = (ez >> 13) == hgen ? (ez & 0x1FFFu) : static_cast<uint32_t>(z);
     }
-    bool killed = false;
-    // The lane-order tests of the swap steps are cheap compares; keep the
-    // compiler from hoisting them into per-step lane masks held (and
-    // spilled) in scalar registers across the loop.
-    int li_v = li;
-    asm volatile("" : "+v"(li_v));
-    fy_batch<G>(std::make_integer_sequence<int, G>{}, li_v, f, j, z, cval, disp, killed);
+    const int32_t jf = li < f ? j : -1 - li;
+    const bool killed =
+        fy_batch<G>(std::make_integer_sequence<int, G>{}, jf, z, cval, disp);
     if (li < f && !killed) pm[j] = static_cast<uint16_t>((hgen << 13) | disp);
     if (li < f) reg_update(c, static_cast<int32_t>(cval) - 1, t, hpos, ind);
     const bool finished = f < nval || z0 + G > k;
@@ -639,7 +725,7 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* 
       if (have) {
         ++z;
         const double E = exp1(draw(P, kTagArrival, static_cast<uint32_t>(z)));
-        const double On = fma(E, 1.0 / static_cast<double>(c.k - z + 1), O);
+        const double On = fma(E, recip_step(c.k - z + 1), O);
         const double t = On * r;
         ++arrivals;
         if (pend) contest_check(c, pend_old, pend_pk);
