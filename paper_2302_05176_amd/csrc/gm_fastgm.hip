@@ -378,8 +378,9 @@ __device__ __forceinline__ uint32_t rec_field(const uint32_t (&d)[rec_dwords<G>(
 }
 
 template <int G>
-__device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy, lds_u16* pm_all,
-                             int pm_stride, double& T) {
+__device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, const lds_i32* counts,
+                             int nlists, int nheavy, lds_i32* claim, lds_u16* pm_all, int pm_stride,
+                             double& T) {
   constexpr int D = rec_dwords<G>();
   const int lane = __lane_id();
   const int row = lane / G;
@@ -393,7 +394,7 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy,
     for (int q2 = lane; q2 < n8; q2 += kWave) z8[q2] = 0ull;
   }
   uint32_t hgen = 0;
-  // the list was written by this wave's lanes with vector stores
+  // the lists were written by the group's lanes with vector stores
   __threadfence_block();
   const int k = c.k;
   bool active = false;
@@ -404,22 +405,32 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy,
   int z0 = 1;
   int batches = 0, elems = 0;  // per segment (statistics only)
   int round = 0;               // wave-uniform batch counter
+  // contest check deferred by one batch (hides the atomic's latency)
+  bool pend = false;
+  unsigned long long pend_old = 0, pend_pk = 0;
   // Each segment holds the record of its next element, loaded when it
   // starts the previous one, so that its load latency is hidden.
   const uint64_t below = row == 0 ? 0ull : (~0ull >> (64 - row * G));
   uint32_t rec[D];
   bool have_rec = false;
-  int next = 0;                // wave-uniform: records handed out
+  bool drained = false;        // wave-uniform: every record has been claimed
+  // Records are claimed from the shared counter, a group of slots per call;
+  // slot g is record g of the lists laid end to end (list u at heavy + u
+  // kHeavyCapG, counts[u] records).
   auto fetch = [&]() {
     const uint64_t need = __ballot(!have_rec && li == 0);
-    if (need && next < nheavy) {
-      const int slot = next + __popcll(need & below);
+    if (need && !drained) {
+      int base = 0;
+      if (lane == 0) base = lds_add(claim, __popcll(need));
+      base = readlane_i32(base, 0);
+      drained = base + __popcll(need) >= nheavy;
+      int slot = base + __popcll(need & below);
       if (!have_rec && slot < nheavy) {
-        rec_load<G>(heavy + slot, li, rec);
+        int u = 0;
+        while (u < nlists - 1 && slot >= counts[u]) slot -= counts[u++];
+        rec_load<G>(heavy + static_cast<int64_t>(u) * kHeavyCapG + slot, li, rec);
         have_rec = true;
       }
-      const int ni = __popcll(need);
-      next += ni < nheavy - next ? ni : nheavy - next;
     }
   };
   fetch();
@@ -457,11 +468,18 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy,
     const bool valid = active && z <= k;
     double E = 0.0, cz = 0.0;
     int32_t j = z;
+    uint32_t ej = 0, ez = 0;
     if (valid) {
-      E = exp1(draw(P, kTagArrival, static_cast<uint32_t>(z)));
-      cz = recip_step(k - z + 1);
       j = randint(draw(P, kTagShuffle, static_cast<uint32_t>(z)), z, k);
+      // the permutation entries, read before the arrival's draw hides their latency
+      ej = pm[j];
+      ez = pm[z];
+      cz = recip_step(k - z + 1);
+      E = exp1(draw(P, kTagArrival, static_cast<uint32_t>(z)));
     }
+    // the previous batch's contest check, now that its atomic has returned
+    if (pend) contest_check(c, pend_old, pend_pk);
+    pend = false;
     // O_z = fma(E_z, c_z, O_{z-1}) in its defined order: after step i lanes
     // 0..i of the segment hold their final value.
     double Ol = fma(E, cz, O);
@@ -480,7 +498,6 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy,
     const int f = rs ? __ffsll(static_cast<long long>(rs)) - 1 : nval;
     uint32_t cval = 0, disp = 0;
     if (li < f) {
-      const uint32_t ej = pm[j], ez = pm[z];
       cval = (ej >> 13) == hgen ? (ej & 0x1FFFu) : static_cast<uint32_t>(j);
       disp = (ez >> 13) == hgen ? (ez & 0x1FFFu) : static_cast<uint32_t>(z);
     }
@@ -488,7 +505,11 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy,
     const bool killed =
         fy_batch<G>(std::make_integer_sequence<int, G>{}, jf, z, cval, disp);
     if (li < f && !killed) pm[j] = static_cast<uint16_t>((hgen << 13) | disp);
-    if (li < f) reg_update(c, static_cast<int32_t>(cval) - 1, t, hpos, ind);
+    if (li < f) {
+      pend_pk = packed_key(c, t, hpos);
+      pend_old = reg_offer(c, static_cast<int32_t>(cval) - 1, t, pend_pk, ind);
+      pend = c.mode == kWalkNormal;
+    }
     const bool finished = f < nval || z0 + G > k;
     O = seg_bcast_f64<G, G - 1>(Ol);
     if (active) {
@@ -501,6 +522,7 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, int nheavy,
     // the republish is a wave-wide reduction: keep its condition wave-uniform
     if (c.mode == kWalkNormal && (++round & 3) == 0) T = fmin(T, wave_max_register(c));
   }
+  if (pend) contest_check(c, pend_old, pend_pk);
   if (c.stats) {
     const int e2 = wave_sum_i32(li == 0 ? elems : 0);
     const int b2 = wave_sum_i32(li == 0 ? batches : 0);
@@ -581,14 +603,17 @@ __host__ __device__ constexpr size_t queue_bytes() { return kQueueCap * (8 + 8 +
 //  (b) lanes without an element pop one from the queue and continue its walk
 //      from step 2; every active lane draws one arrival.
 // Elements expected to walk long, and those whose displaced-position table
-// fills up, are listed in `hl` (device memory) for the segment path.  That
-// path runs once nothing is in flight on the light path -- at the end of the
-// walk, or earlier when the list is nearly full (probing then pauses until
-// the queue and the lanes drain) -- and reuses the LDS of the queue and the
-// tables for its permutations; the tables are cleared afterwards.
+// fills up, are listed in `hl` (device memory) for the segment path.  When
+// the list is nearly full, probing pauses until nothing is in flight on the
+// light path, and the wave walks its list alone (`pclaim`: its own claim
+// counter); the list left at the end of the walk is returned, for the whole
+// group to share.  The segment path reuses the LDS of the queue and the
+// tables for its permutations (a lane trusts only the table slots its slot
+// mask marks, so nothing needs clearing).  T is the threshold, tightened as
+// registers improve.
 template <int G>
-__device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* hl, lds_u16* pm,
-                          int pm_stride, lds_u32* mp, const Queue& q) {
+__device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* hl, lds_u16* pm,
+                         int pm_stride, lds_u32* mp, const Queue& q, lds_i32* pclaim) {
   const int lane = __lane_id();
   const double c1 = 1.0 / static_cast<double>(c.k);
   bool have = false;
@@ -783,13 +808,14 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* 
         contest_check(c, pend_old, pend_pk);
         pend = false;
       }
+      if (!more) break;
       if (nheavy > 0) {
         const uint64_t c0 = c.stats ? clock64() : 0;
-        segment_walk<G>(c, hl, nheavy, pm, pm_stride, T);
+        if (lane == 0) *pclaim = 0;
+        segment_walk<G>(c, hl, nullptr, 1, nheavy, pclaim, pm, pm_stride, T);
         if (c.stats && lane == 0) stat_add(c.stats, kStCycSeg, clock64() - c0);
         nheavy = 0;
       }
-      if (!more) break;
     }
   }
   if (c.stats) {
@@ -803,6 +829,7 @@ __device__ void walk_wave(const VecCtx& c, lds_i32* cursor, double T, HeavyRec* 
       stat_add(c.stats, kStElements, static_cast<unsigned long long>(st));
     }
   }
+  return nheavy;
 }
 
 // (1 - p) quantile of the maximum of k Exp(1) variables: a vector's final
@@ -853,6 +880,9 @@ struct FgShared {
   int contest;
   int bad;
   int task;
+  int hclaim;       // claim counter of the group's final heavy lists
+  int hcount[16];   // records in each wave's final list
+  int pclaim[16];   // each wave's own claim counter (lists walked alone)
   double wsum[16];
   unsigned long long wmax[16];
 };
@@ -1032,8 +1062,25 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   // big vectors keep the quantile their candidate lists were cut at
   double T = fmin(max_exp_quantile(d.k, bi ? 1e-4 : kFirstMiss) * fa.t0_scale / S, cap);
   bool resolve = false;
+  lds_i32* pclaim = (lds_i32*)(&sh.pclaim[wave]);
+  lds_i32* hcount = (lds_i32*)(&sh.hcount[0]);
+  lds_i32* hclaim = (lds_i32*)(&sh.hclaim);
   for (int pass = 0;; ++pass) {
-    walk_wave<G>(c, cursor, T, hl, pm, pm_stride, mp, q);
+    double Tw = T;
+    const int nh = walk_wave<G>(c, cursor, Tw, hl, pm, pm_stride, mp, q, pclaim);
+    // The waves' final heavy lists are walked by the whole group, each wave
+    // claiming records from all of them: no wave waits on another's list.
+    if (lane == 0) hcount[wave] = nh;
+    if (tid == 0) *hclaim = 0;
+    group_sync<GW>();
+    int total = 0;
+    for (int u = 0; u < GW; ++u) total += hcount[u];
+    if (total > 0) {
+      const uint64_t c0 = timed ? clock64() : 0;
+      segment_walk<G>(c, hl - static_cast<int64_t>(wave) * kHeavyCapG, hcount, GW, total, hclaim, pm,
+                      pm_stride, Tw);
+      if (timed && lane == 0) stat_add(fa.stats, kStCycSeg, clock64() - c0);
+    }
     group_sync<GW>();
     lap(pass == 0 ? kStCycWalk : kStCycExtra);
     if (resolve) break;
