@@ -217,13 +217,13 @@ gm_status gm_reset_data_errors(hipStream_t stream);
  *   GM_OPT_T0_SCALE_PPM  [1000000] scale of the closed-form pruning threshold
  *                        in parts per million; small values force the
  *                        enlarge-and-repeat fallback.
- *   GM_OPT_MAP_LOAD      [10] displaced permutation positions a lane may
+ *   GM_OPT_MAP_LOAD      [14] displaced permutation positions a lane may
  *                        track, 0..16; beyond it an element moves to the
  *                        segment path, where 16 or 64 lanes walk it
  *                        together (0 sends almost every element there).
- *   GM_OPT_REPUBLISH     [4] light iterations between republishes of the
+ *   GM_OPT_REPUBLISH     [8] light iterations between republishes of the
  *                        running maximum register, a power of two.
- *   GM_OPT_SEG_REST      [16] an element whose expected number of further
+ *   GM_OPT_SEG_REST      [12] an element whose expected number of further
  *                        arrivals below the threshold (k v_i (T - t_1))
  *                        exceeds this goes to the segment path straight
  *                        from its first arrival, 0..1000000 (0: every

@@ -77,9 +77,9 @@ DeviceState g_dev[kMaxDevices];
 // Tuning / testing options (process-wide).
 int g_pos_bits = 24;
 double g_t0_scale = 1.0;
-int g_map_load = 10;
-int g_republish = 4;
-double g_seg_rest = 16.0;
+int g_map_load = 14;
+int g_republish = 8;
+double g_seg_rest = 12.0;
 int g_small_waves = 0;
 bool g_stats = false;
 

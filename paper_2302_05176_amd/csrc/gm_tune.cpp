@@ -149,7 +149,7 @@ extern "C" gm_status gm_autotune(const int32_t* indices, const float* weights,
   if (e == hipSuccess) e = hipMemcpy(&ends[1], offsets + nvec, sizeof(int64_t), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return GM_ERR_DEVICE;
   const std::string key = cache_key(k_max, nvec, ends[1] - ends[0], batched);
-  Knobs best{0, 10, 16, 4};
+  Knobs best{0, 14, 12, 8};
   double best_ms = 0.0;
   if (use_cache && cache_lookup(key, best, best_ms)) {
     gm_status s = set_knobs(best);
@@ -196,9 +196,9 @@ extern "C" gm_status gm_autotune(const int32_t* indices, const float* weights,
   };
   gm_status s = time_knobs(best, best_ms);
   const std::vector<int64_t> grid_waves = {0, 1, 2, 4, 8};
-  const std::vector<int64_t> grid_seg = {8, 16, 32, 64};
-  const std::vector<int64_t> grid_map = {6, 10, 16};
-  const std::vector<int64_t> grid_rep = {2, 4, 8, 16};
+  const std::vector<int64_t> grid_seg = {4, 8, 12, 16, 32, 64};
+  const std::vector<int64_t> grid_map = {8, 10, 12, 14, 16};
+  const std::vector<int64_t> grid_rep = {4, 8, 16};
   for (int axis = 0; axis < 4 && s == GM_OK; ++axis) {
     const std::vector<int64_t>& grid =
         axis == 0 ? grid_waves : axis == 1 ? grid_seg : axis == 2 ? grid_map : grid_rep;
