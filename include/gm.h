@@ -231,8 +231,11 @@ gm_status gm_reset_data_errors(hipStream_t stream);
  *   GM_OPT_SMALL_WAVES   [0] waves per workgroup of the kernels for vectors
  *                        of up to 32768 entries (0: chosen from k; else
  *                        1, 2, 4 or 8).
- *   GM_OPT_TIMING        [0] 1 brackets every sketch-kernel launch with HIP
- *                        events on its stream (read with gm_get_timing).
+ *   GM_OPT_TIMING        [0] 1 brackets every launch of a sketch call with
+ *                        HIP events on its stream (read with gm_get_timing);
+ *                        2 only the sketch kernels themselves (FastGM class
+ *                        kernels and the plain kernel), not the planning and
+ *                        big-vector passes: fewer events in a timed loop.
  *   GM_OPT_STATS         [0] 1 makes FastGM calls accumulate work counters
  *                        (read them with gm_get_stats); costs a few atomics
  *                        per vector.
@@ -268,7 +271,7 @@ gm_status gm_reset_stats(hipStream_t stream);
 
 /*
  * gm_get_timing -- waits for the timed launches made while GM_OPT_TIMING
- * was 1, then copies up to n entries: kernel name (as the profiler names the
+ * was 1 or 2, then copies up to n entries: kernel name (as the profiler names the
  * instance), total milliseconds and launch count.  Returns the number of
  * entries copied.  gm_reset_timing clears the totals.
  */

@@ -254,7 +254,7 @@ def get_stats(stream=None) -> dict:
 
 
 def get_timing() -> dict:
-    """Per-kernel HIP-event totals of launches made while set_option("timing", 1):
+    """Per-kernel HIP-event totals of launches made while set_option("timing", 1 or 2):
     {kernel name: (total ms, launches)}."""
     L = _native.load()
     n = 64

@@ -19,7 +19,7 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
                          unsigned long long* stats, hipStream_t stream);
 size_t plan_state_bytes();
 int64_t heavy_list_bytes();
-void timing_enable(bool on);
+void timing_enable(int level);
 int timing_collect(int n, char (*names)[64], double* ms, long long* launches);
 void timing_reset();
 size_t big_info_bytes();
@@ -329,10 +329,10 @@ gm_status gm_set_option(gm_option opt, int64_t value) {
       g_small_waves = static_cast<int>(value);
       return GM_OK;
     case GM_OPT_TIMING:
-      if (value != 0 && value != 1) return GM_ERR_INVALID_ARG;
+      if (value < 0 || value > 2) return GM_ERR_INVALID_ARG;
       {
         std::lock_guard<std::mutex> lock(g_mu);
-        gm::timing_enable(value != 0);
+        gm::timing_enable(static_cast<int>(value));
       }
       return GM_OK;
     case GM_OPT_STATS:

@@ -544,18 +544,25 @@ struct LaneMap {
   uint64_t bloom;
 };
 
+// Home slot of position p.
+__device__ __forceinline__ int map_home(uint32_t p) {
+  return static_cast<int>((p - 1) & (kMapSlots - 1));
+}
+
 // Value at position p (p if not displaced); `slot` receives p's slot when
-// found, `found` whether p was present.
+// found, `found` whether p was present.  `home` is the word of p's home slot,
+// read ahead by the caller (trusted only where the slot mask marks the slot).
 __device__ __forceinline__ uint32_t map_find(const lds_u32* mp, const LaneMap& m, uint32_t p,
-                                             int& slot, bool& found) {
+                                             uint32_t home, int& slot, bool& found) {
   found = false;
   slot = -1;
   if (((m.bloom >> (p & 63u)) & 1ull) == 0) return p;
   const uint32_t key = p - 1;
-  int s = static_cast<int>(key & (kMapSlots - 1));
+  int s = map_home(p);
+  uint32_t e = home;
   for (int q = 0; q < kMapSlots; ++q) {
     if (((m.occ >> s) & 1u) == 0) return p;
-    const uint32_t e = mp[s * kWave];
+    if (q > 0) e = mp[s * kWave];
     if ((e >> 12) == key) {
       slot = s;
       found = true;
@@ -749,6 +756,8 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
     if (any_have) {
       if (have) {
         ++z;
+        // the home slot of position z, read ahead of the arrival's draw
+        const uint32_t hz = mp[map_home(static_cast<uint32_t>(z)) * kWave];
         const double E = exp1(draw(P, kTagArrival, static_cast<uint32_t>(z)));
         const double On = fma(E, recip_step(c.k - z + 1), O);
         const double t = On * r;
@@ -760,10 +769,11 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
         } else {
           ++kept;
           const int32_t j = randint(draw(P, kTagShuffle, static_cast<uint32_t>(z)), z, c.k);
+          const uint32_t hj = mp[map_home(static_cast<uint32_t>(j)) * kWave];
           int zslot, jslot;
           bool zfound, jfound;
-          const uint32_t vz = map_find(mp, lm, static_cast<uint32_t>(z), zslot, zfound);
-          const uint32_t vj = map_find(mp, lm, static_cast<uint32_t>(j), jslot, jfound);
+          const uint32_t vz = map_find(mp, lm, static_cast<uint32_t>(z), hz, zslot, zfound);
+          const uint32_t vj = map_find(mp, lm, static_cast<uint32_t>(j), hj, jslot, jfound);
           if (j != z) {
             // position j now holds the value position z held
             if (!jfound) {
@@ -1480,7 +1490,7 @@ struct TimedLaunch {
 };
 
 struct TimingState {
-  bool on = false;
+  int level = 0;  // 0 off, 1 every launch, 2 the sketch kernels only
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> free_events;
   std::vector<std::string> names;
@@ -1493,7 +1503,7 @@ TimingState& timing() {
   return t;
 }
 
-void timing_enable(bool on) { timing().on = on; }
+void timing_enable(int level) { timing().level = level; }
 
 static int timing_id(const std::string& name) {
   TimingState& t = timing();
@@ -1517,9 +1527,12 @@ static hipEvent_t timing_event() {
   return e;
 }
 
-// Bracket one launch (returns -1 when timing is off).
-static int timing_begin(const std::string& name, hipStream_t stream, hipEvent_t* a) {
-  if (!timing().on) return -1;
+// Bracket one launch (returns -1 when timing is off).  `main`: a sketch
+// kernel (FastGM class or plain), timed at both levels; the planning and
+// big-vector passes only at level 1.
+static int timing_begin(const char* name, bool main, hipStream_t stream, hipEvent_t* a) {
+  const int level = timing().level;
+  if (level == 0 || (level == 2 && !main)) return -1;
   *a = timing_event();
   (void)hipEventRecord(*a, stream);
   return timing_id(name);
@@ -1564,7 +1577,7 @@ void timing_reset() {
 }
 
 int timing_begin_plain(hipStream_t stream, hipEvent_t* a) {
-  return timing_begin("plain_kernel", stream, a);
+  return timing_begin("plain_kernel", true, stream, a);
 }
 void timing_end_plain(int id, hipEvent_t a, hipStream_t stream) { timing_end(id, a, stream); }
 
@@ -1599,9 +1612,9 @@ static hipError_t launch_class(const FastArgs& fa, int cus, hipStream_t stream) 
   if (grid < 1) return hipErrorInvalidValue;
   hipEvent_t ta = nullptr;
   // named as rocprofv3 names the kernel, plus the class it drains
-  const int tid = timing_begin("fastgm_class_kernel<" + std::to_string(W) + ", " +
-                                   std::to_string(G) + "> [class " + std::to_string(fa.cls) + "]",
-                               stream, &ta);
+  char name[64];
+  std::snprintf(name, sizeof(name), "fastgm_class_kernel<%d, %d> [class %d]", W, G, fa.cls);
+  const int tid = timing_begin(name, true, stream, &ta);
   hipLaunchKernelGGL((fastgm_class_kernel<W, G>), dim3(static_cast<unsigned>(grid)), dim3(W * kWave),
                      lds, stream, fa);
   timing_end(tid, ta, stream);
@@ -1644,26 +1657,28 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
   fa.list = list;
   fa.plan = static_cast<PlanState*>(plan);
   hipEvent_t ta = nullptr;
-  int tid = timing_begin("plan_kernel", stream, &ta);
+  int tid = timing_begin("plan_kernel", false, stream, &ta);
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, stream, s, list, fa.plan, fa.big,
                      pool_cap, t0_scale, kLimM);
   timing_end(tid, ta, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  tid = timing_begin("big_sum_kernel", stream, &ta);
+  tid = timing_begin("big_sum_kernel", false, stream, &ta);
   hipLaunchKernelGGL(big_sum_kernel, dim3(cus * 4), dim3(kBigBlock), 0, stream, fa);
   timing_end(tid, ta, stream);
-  tid = timing_begin("big_probe_kernel", stream, &ta);
+  tid = timing_begin("big_probe_kernel", false, stream, &ta);
   hipLaunchKernelGGL(big_probe_kernel, dim3(cus * 8), dim3(kBigBlock), 0, stream, fa);
   timing_end(tid, ta, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // One persistent kernel per (size class, k class) that k_max can reach;
-  // an empty class exits at once.
+  // One persistent kernel per (size class, k class) that the call's k can
+  // reach; an empty class exits at once.
   for (int sc = 0; sc < kSizeClasses; ++sc) {
     for (int kc = 0; kc < kKClasses; ++kc) {
       const int lo = kc == 0 ? 1 : kclass_hi(kc - 1) + 1;
       if (lo > s.k_max) break;
+      // one k for every vector: the other k ranges are empty
+      if (!s.kvec && kclass_hi(kc) < s.k_uniform) continue;
       fa.cls = sc * kKClasses + kc;
       fa.lds_k = s.k_max < kclass_hi(kc) ? s.k_max : kclass_hi(kc);
       int waves = 1;
