@@ -338,15 +338,36 @@ __device__ __forceinline__ void fy_step(int32_t j, int32_t z, uint32_t& cval, ui
   after = (after << 1) & after;
 }
 
+// Swap step L when no step of the batch targets a position the batch reaches
+// later: every lane's displaced value is final from the start, and only
+// duplicate targets interact.
+template <int G, int L>
+__device__ __forceinline__ void fy_step_flat(int32_t j, uint32_t& cval, uint32_t disp,
+                                             uint64_t& after, uint64_t& before, uint64_t& killm) {
+  const uint32_t dl = seg_bcast<G, L>(disp);
+  const int32_t jl = static_cast<int32_t>(seg_bcast<G, L>(static_cast<uint32_t>(j)));
+  const uint64_t eqj = __ballot(j == jl);
+  cval = __builtin_amdgcn_inverse_ballot_w64(eqj & after) ? dl : cval;
+  killm |= eqj & before;
+  before = (before << 1) | seg_first_lanes<G>();
+  after = (after << 1) & after;
+}
+
+// `inwin`: some lane of the wave swaps with a position of its own batch
+// beyond its step (z_L < j_L <= the batch's last step), so that a later
+// step's displaced value changes during the batch.
 template <int G, int... Ls>
 __device__ __forceinline__ bool fy_batch(std::integer_sequence<int, Ls...>, int32_t j, int32_t z,
-                                         uint32_t& cval, uint32_t& disp) {
+                                         bool inwin, uint32_t& cval, uint32_t& disp) {
   uint64_t after = ~seg_first_lanes<G>(), before = 0, killm = 0;
   // computed step by step with two scalar operations each: folded to
   // constants, the masks of all steps would be hoisted and held in scalar
   // registers across the whole walk
   asm volatile("" : "+s"(after), "+s"(before));
-  (fy_step<G, Ls>(j, z, cval, disp, after, before, killm), ...);
+  if (inwin)
+    (fy_step<G, Ls>(j, z, cval, disp, after, before, killm), ...);
+  else
+    (fy_step_flat<G, Ls>(j, cval, disp, after, before, killm), ...);
   return __builtin_amdgcn_inverse_ballot_w64(killm);
 }
 
@@ -484,10 +505,13 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, const lds_i
     // 0..i of the segment hold their final value.
     double Ol = fma(E, cz, O);
     double prev = O;
+    // (E >= +0, so |E| is E; the modifier selects the three-operand FMA,
+    // which leaves `prev` intact for the next shift instead of copying it)
+    const double Ea = fabs(E);
 #pragma unroll
     for (int i = 1; i < G; ++i) {
       prev = seg_shr1<G>(Ol, prev);
-      Ol = fma(E, cz, prev);
+      Ol = fma(Ea, cz, prev);
     }
     const double t = Ol * r;
     const uint64_t stopm = __ballot(valid && t > T);
@@ -502,8 +526,9 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, const lds_i
       disp = (ez >> 13) == hgen ? (ez & 0x1FFFu) : static_cast<uint32_t>(z);
     }
     const int32_t jf = li < f ? j : -1 - li;
+    const bool inwin = __ballot(li < f && j > z && j < z0 + f) != 0;
     const bool killed =
-        fy_batch<G>(std::make_integer_sequence<int, G>{}, jf, z, cval, disp);
+        fy_batch<G>(std::make_integer_sequence<int, G>{}, jf, z, inwin, cval, disp);
     if (li < f && !killed) pm[j] = static_cast<uint16_t>((hgen << 13) | disp);
     if (li < f) {
       pend_pk = packed_key(c, t, hpos);
