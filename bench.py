@@ -64,14 +64,18 @@ def harmonic(k: int) -> float:
     return sum(1.0 / m for m in range(1, k + 1))
 
 
+# Sources that build the measured sketch kernels or set their launch
+# parameters: a change to any of them makes committed counters stale.
+DIGEST_SOURCES = ["paper_2302_05176_amd/csrc/gm_fastgm.hip", "paper_2302_05176_amd/csrc/gm_plain.hip",
+                  "paper_2302_05176_amd/csrc/gm_api.hip", "paper_2302_05176_amd/csrc/gm_common.h",
+                  "paper_2302_05176_amd/csrc/gm_draw.h", "include/gm.h"]
+
+
 def source_digest() -> str:
-    csrc = os.path.join(ROOT, "paper_2302_05176_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(csrc)):
-        if not name.endswith((".hip", ".h", ".cpp")):
-            continue
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode())
+    for rel in DIGEST_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode())
             h.update(f.read())
     return h.hexdigest()
 
