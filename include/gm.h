@@ -197,6 +197,43 @@ gm_status gm_merge(const int32_t *in_idx, const double *in_val, int64_t r, int32
                    int32_t *out_idx, double *out_val, hipStream_t stream);
 
 /*
+ * LSH index over stored sketches (Sec. 1: each register maps similar vectors
+ * to the same element with probability J_P, so the registers can key a
+ * locality-sensitive index that finds similar vectors in sub-linear time).
+ *
+ * Band b (0 <= b < bands) of a sketch is its registers b*rows .. b*rows +
+ * rows - 1.  A stored row is a candidate for a query when, in at least one
+ * band, all `rows` register indices are equal and non-negative (an empty or
+ * poisoned register never matches).  A pair at probability-Jaccard J is a
+ * candidate with probability 1 - (1 - J^rows)^bands.
+ *
+ * gm_lsh_build -- indexes store_idx [nstore][k] int32 (device, caller-owned;
+ *   it must stay allocated and unchanged while the index is used: queries
+ *   verify candidates against it).  1 <= bands <= 64, rows >= 1, bands*rows
+ *   <= k.  Allocates the index (12 bytes per row and band, plus the sort's
+ *   temporaries during the call) with hipMalloc and synchronises `stream`:
+ *   not for graph capture.  *out receives an index owned by the library;
+ *   release it with gm_lsh_free.  GM_ERR_UNSUPPORTED when nstore*bands >
+ *   2^31 - 1.
+ * gm_lsh_query -- for nq queries query_idx [nq][k] int32 (device): count[q]
+ *   (device int32) = the number of distinct candidate rows, and cand[q][0 ..
+ *   min(count, max_cand) - 1] (device int32, [nq][max_cand]) = the smallest
+ *   of them in ascending order.  A query with more than 2048 band matches
+ *   (before duplicates across bands are removed) gets count = -1 and no
+ *   candidates.  Asynchronous on `stream`.
+ * gm_lsh_info -- the index's shape (any output pointer may be null).
+ * gm_lsh_free -- releases an index (null is ignored).
+ */
+typedef struct gm_lsh_index gm_lsh_index;
+gm_status gm_lsh_build(const int32_t *store_idx, int64_t nstore, int32_t k, int32_t bands,
+                       int32_t rows, gm_lsh_index **out, hipStream_t stream);
+gm_status gm_lsh_query(const gm_lsh_index *index, const int32_t *query_idx, int64_t nq,
+                       int32_t max_cand, int32_t *cand, int32_t *count, hipStream_t stream);
+gm_status gm_lsh_info(const gm_lsh_index *index, int64_t *nstore, int32_t *k, int32_t *bands,
+                      int32_t *rows);
+void gm_lsh_free(gm_lsh_index *index);
+
+/*
  * gm_get_data_errors -- synchronises `stream`, then stores in *host_count the
  * number of poisoned vectors (and invalid store rows) seen on the current
  * device since the library was loaded or last reset.

@@ -181,6 +181,53 @@ def merge(idx, val, stream=None):
     return oi, ov
 
 
+class LshIndex:
+    """Banding LSH index over a device sketch store (gm_lsh_build): band b is
+    registers b*rows .. b*rows+rows-1; a stored row is a candidate for a query
+    when some band's indices are all equal and non-negative.  Holds a
+    reference to the store, which queries read."""
+
+    def __init__(self, store, bands: int, rows: int, stream=None):
+        torch = _torch()
+        L = _native.load()
+        nstore, k = store.shape
+        h = ctypes.c_void_p()
+        st = L.gm_lsh_build(_dev(store, torch.int32, "store"), nstore, k, bands, rows,
+                            ctypes.byref(h), _stream(stream))
+        _native.check(st, "gm_lsh_build")
+        self._h = h
+        self.store = store
+        self.k, self.bands, self.rows = k, bands, rows
+
+    def query(self, queries, max_cand: int = 64, stream=None):
+        """Candidates of [nq, k] query sketches: (cand [nq, max_cand] int32, the
+        smallest candidate rows in ascending order; count [nq] int32, the number
+        of distinct candidates, -1 past 2048 band matches)."""
+        torch = _torch()
+        L = _native.load()
+        nq = queries.shape[0]
+        if queries.shape[1] != self.k:
+            raise ValueError("queries must have the index's k registers")
+        cand = torch.full((nq, max(max_cand, 1)), -1, dtype=torch.int32, device=queries.device)
+        count = torch.empty(nq, dtype=torch.int32, device=queries.device)
+        st = L.gm_lsh_query(self._h, _dev(queries, torch.int32, "queries"), nq, max_cand,
+                            _dev(cand, torch.int32, "cand"), _dev(count, torch.int32, "count"),
+                            _stream(stream))
+        _native.check(st, "gm_lsh_query")
+        return cand[:, :max_cand], count
+
+    def close(self):
+        if self._h:
+            _native.load().gm_lsh_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def rate_probe(what: str, lanes: int, steps: int, seed: int = 1, out=None, stream=None):
     """Issue-rate probe (gm_rate_probe): `lanes` lanes each draw `steps` FastGM
     arrivals (what="arrivals") or plain keys (what="keys"); returns the

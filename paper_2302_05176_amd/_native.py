@@ -66,6 +66,12 @@ def load() -> ctypes.CDLL:
     L.gm_wcard_est.argtypes = [p, i64, i32, p, p]
     L.gm_merge.argtypes = [p, p, i64, i32, p, p, p]
     L.gm_rate_probe.argtypes = [i32, i64, i32, u64, p, p]
+    L.gm_lsh_build.argtypes = [p, i64, i32, i32, i32, ctypes.POINTER(p), p]
+    L.gm_lsh_query.argtypes = [p, p, i64, i32, p, p, p]
+    L.gm_lsh_info.argtypes = [p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.gm_lsh_free.argtypes = [p]
+    L.gm_lsh_free.restype = None
     L.gm_get_data_errors.argtypes = [ctypes.POINTER(ctypes.c_int64), p]
     L.gm_reset_data_errors.argtypes = [p]
     L.gm_set_option.argtypes = [ctypes.c_int, i64]
@@ -88,7 +94,7 @@ def load() -> ctypes.CDLL:
     for name in ("gm_sketch", "gm_sketch_plain", "gm_sketch_batched", "gm_jaccard_est",
                  "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_get_data_errors",
                  "gm_reset_data_errors", "gm_set_option", "gm_get_stats", "gm_reset_stats", "gm_reserve", "gm_autotune",
-                 "gm_serve_run"):
+                 "gm_serve_run", "gm_lsh_build", "gm_lsh_query", "gm_lsh_info"):
         getattr(L, name).restype = st
     _lib = L
     return L

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgm.so")
 SOURCES = ["gm_api.hip", "gm_plain.hip", "gm_fastgm.hip", "gm_estimators.hip", "gm_rates.hip",
-           "gm_tune.cpp", "gm_serve.cpp"]
+           "gm_lsh.hip", "gm_tune.cpp", "gm_serve.cpp"]
 HEADERS = ["gm_common.h", "gm_draw.h"]
 ARCH = os.environ.get("GM_OFFLOAD_ARCH", "gfx950")
 

@@ -29,7 +29,7 @@ def test_header_declares_expected_entry_points():
     for s in ("gm_sketch", "gm_sketch_plain", "gm_sketch_batched", "gm_sketch_update",
               "gm_jaccard_est",
               "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_get_data_errors",
-              "gm_release"):
+              "gm_lsh_build", "gm_lsh_query", "gm_lsh_free", "gm_release"):
         assert s in syms
 
 
@@ -65,6 +65,17 @@ def test_host_side_argument_validation(lib):
     assert lib.gm_rate_probe(0, 64, 0, u, fake, nul) == N.GM_ERR_INVALID_ARG
     assert lib.gm_rate_probe(0, 64, 8, u, nul, nul) == N.GM_ERR_INVALID_ARG
     assert lib.gm_rate_probe(1, 0, 8, u, nul, nul) == N.GM_OK
+    h = ctypes.c_void_p()
+    assert lib.gm_lsh_build(nul, 10, 16, 4, 4, ctypes.byref(h), nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_lsh_build(fake, 10, 16, 0, 4, ctypes.byref(h), nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_lsh_build(fake, 10, 16, 65, 1, ctypes.byref(h), nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_lsh_build(fake, 10, 16, 5, 4, ctypes.byref(h), nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_lsh_build(fake, 10, 16, 4, 4, None, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_lsh_build(fake, 1 << 30, 64, 16, 4, ctypes.byref(h), nul) == N.GM_ERR_UNSUPPORTED
+    assert not h.value
+    assert lib.gm_lsh_query(nul, fake, 1, 4, fake, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_lsh_info(nul, None, None, None, None) == N.GM_ERR_INVALID_ARG
+    lib.gm_lsh_free(nul)
     # empty work is a no-op
     assert lib.gm_sketch(nul, nul, nul, 0, 8, u, nul, nul, nul) == N.GM_OK
     assert lib.gm_jaccard_est(nul, nul, 0, 8, nul, nul) == N.GM_OK
