@@ -162,7 +162,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["batch", "single", "stream", "stream_update", "uneven",
-                                           "serve", "rates"],
+                                           "serve", "rates", "lsh"],
                     default="batch")
     ap.add_argument("--form", choices=["fastgm", "plain"], default="fastgm")
     ap.add_argument("--k", type=int, default=256)
@@ -523,6 +523,78 @@ def bench_serve(args):
                       "store_build_s": build_s}), flush=True)
 
 
+def bench_lsh(args):
+    """LSH index over 1e6 stored sketches (k = 512, 64 bands x 6 registers):
+    build time, query throughput, and recall of each perturbed query's source
+    row against the banding curve 1 - (1 - J^6)^64."""
+    import numpy as np
+    import torch
+
+    import paper_2302_05176_amd as gm
+    dev = torch.device("cuda:0")
+    nstore, k, n, bands, rows = 1_000_000, 512, 32, 64, 6
+    nq_near, nq_far = 10_000, 10_000
+    rng = np.random.Generator(np.random.PCG64(1013))
+    # stored vectors: n distinct indices in [0, 2^24) (duplicates within a row
+    # are rare and harmless), Exp(1) weights
+    si = rng.integers(0, 1 << 24, size=(nstore, n), dtype=np.int64).astype(np.int32)
+    sw = (rng.exponential(1.0, size=(nstore, n)) + 1e-6).astype(np.float32)
+    store = torch.empty((nstore, k), dtype=torch.int32, device=dev)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to(dev)
+    for s0 in range(0, nstore, 250_000):
+        m = min(250_000, nstore - s0)
+        gm.sketch(t(si[s0:s0 + m]), t(sw[s0:s0 + m]), t(np.arange(m + 1, dtype=np.int64) * n), k,
+                  args.seed, out_idx=store[s0:s0 + m])
+    # near queries: a stored row with 4 of its 32 entries replaced; far: fresh
+    src = rng.integers(0, nstore, size=nq_near)
+    qi = np.concatenate([si[src], rng.integers(0, 1 << 24, size=(nq_far, n)).astype(np.int32)])
+    qw = np.concatenate([sw[src], (rng.exponential(1.0, size=(nq_far, n)) + 1e-6).astype(np.float32)])
+    repl = rng.integers(0, n, size=(nq_near, 4))
+    for c in range(4):
+        qi[np.arange(nq_near), repl[:, c]] = rng.integers(1 << 24, 1 << 25, size=nq_near)
+        qw[np.arange(nq_near), repl[:, c]] = (rng.exponential(1.0, size=nq_near) + 1e-6).astype(np.float32)
+    nq = nq_near + nq_far
+    queries = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    gm.sketch(t(qi), t(qw), t(np.arange(nq + 1, dtype=np.int64) * n), k, args.seed, out_idx=queries)
+    torch.cuda.synchronize()
+    # the probability-Jaccard of a near query with its source (same weights on
+    # the kept entries, disjoint replacements): sum kept / (sum of both)
+    kept = np.ones((nq_near, n), bool)
+    kept[np.arange(nq_near)[:, None], repl] = False
+    a = sw[src].astype(np.float64)
+    b = qw[:nq_near].astype(np.float64)
+    shared = (a * kept).sum(1)
+    jp = shared / (a.sum(1) + b.sum(1) - shared)
+    expect = 1.0 - (1.0 - jp ** rows) ** bands
+    t0 = time.perf_counter()
+    ix = gm.LshIndex(store, bands, rows)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    max_cand = 16
+    ms, _ = timed_steps(lambda: ix.query(queries, max_cand), 5, 2, torch.cuda.current_stream())
+    cand, count = ix.query(queries, max_cand)
+    torch.cuda.synchronize()
+    cand, count = cand.cpu().numpy(), count.cpu().numpy()
+    found = np.array([src[q] in cand[q, :min(count[q], max_cand)] for q in range(nq_near)])
+    # brute force for comparison: the Jaccard estimate of one pair per stored row
+    ia = torch.randint(0, nstore, (nstore,), device=dev)
+    ib = torch.randint(0, nstore, (nstore,), device=dev)
+    jout = torch.empty(nstore, dtype=torch.float64, device=dev)
+    scan_ms, _ = timed_steps(lambda: gm.jaccard_est_pairs(store, ia, ib, out=jout), 5, 2,
+                             torch.cuda.current_stream())
+    ix.close()
+    print(json.dumps({
+        "workload": "LSH index: 1e6 stored sketches (k=512, 32-entry vectors), 64 bands x 6 "
+                    "registers; 1e4 queries = stored vectors with 4 of 32 entries replaced, "
+                    "1e4 unrelated",
+        "build_ms": build_ms, "queries": nq, "query_ms": ms, "queries_per_s": nq / (ms / 1e3),
+        "near_recall": float(found.mean()), "near_recall_expected": float(expect.mean()),
+        "near_mean_candidates": float(count[:nq_near].mean()),
+        "far_mean_candidates": float(count[nq_near:].mean()),
+        "overflowed": int((count < 0).sum()),
+        "brute_force_scan_ms_per_query": scan_ms,
+        "speedup_vs_scan": scan_ms / (ms / nq)}), flush=True)
+
+
 def main():
     args = parse()
     if args.summarize_pmc:
@@ -540,7 +612,7 @@ def main():
     torch.cuda.set_device(0)
     {"batch": bench_batch, "single": bench_single, "stream": bench_stream,
      "uneven": bench_uneven, "serve": bench_serve, "rates": bench_rates,
-     "stream_update": bench_stream_update}[args.workload](args)
+     "stream_update": bench_stream_update, "lsh": bench_lsh}[args.workload](args)
 
 
 if __name__ == "__main__":
