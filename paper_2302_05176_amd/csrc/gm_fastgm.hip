@@ -115,7 +115,10 @@ struct PlanState {
 // the entries whose first arrival is within the closed-form threshold T0.
 // Only those can reach a register once y* <= T0 (an element's arrivals only
 // grow), so the walk visits the candidates instead of the whole vector.
-constexpr int64_t kBigChunk = 65536;
+// The passes hand out chunks of kBigChunk entries, one per workgroup at a
+// time: small enough that one 10^7-entry vector spreads over every CU (1221
+// chunks of 8192).
+constexpr int64_t kBigChunk = 8192;
 
 struct BigInfo {
   int64_t chunk_base;    // first chunk of this vector
@@ -1394,7 +1397,26 @@ __global__ __launch_bounds__(kBigBlock) void big_sum_kernel(FastArgs fa) {
     if (tid == 0) sbad = 0;
     double part = 0.0;
     bool badl = false;
-    for (int64_t e = e0 + tid; e < e1; e += kBigBlock) {
+    // eight independent loads per lane in flight per step
+    constexpr int kU = 8;
+    int64_t e = e0 + tid;
+    for (; e + (kU - 1) * kBigBlock < e1; e += kU * kBigBlock) {
+      int32_t iv[kU];
+      float wv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        iv[u] = p.idx[e + u * kBigBlock];
+        wv[u] = p.w[e + u * kBigBlock];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (iv[u] < 0 || !weight_valid(wv[u]))
+          badl = true;
+        else
+          part += static_cast<double>(wv[u]);
+      }
+    }
+    for (; e < e1; e += kBigBlock) {
       const int32_t i = p.idx[e];
       const float wv = p.w[e];
       if (i < 0 || !weight_valid(wv))
@@ -1420,6 +1442,8 @@ __global__ __launch_bounds__(kBigBlock) void big_sum_kernel(FastArgs fa) {
 // Grid-wide pass 2 over big vectors: first arrival of every entry; entries
 // within T0 go to the vector's candidate list.
 __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
+  __shared__ int32_t slist[kBigChunk];
+  __shared__ int scount, sbase;
   const SketchArgs& p = fa.s;
   int c2 = 0;
   for (int cc = kBigFirst; cc < kNumClasses; ++cc) c2 += fa.plan->count[cc];
@@ -1459,6 +1483,11 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
     const double c1 = 1.0 / static_cast<double>(d.k);
     const int64_t e0 = d.a + (t - bi->chunk_base) * kBigChunk;
     const int64_t e1 = e0 + kBigChunk < d.b ? e0 + kBigChunk : d.b;
+    // The chunk's candidates are gathered in LDS and the vector's list takes
+    // them with one atomic: one counter per vector, hit by every wave, would
+    // serialise the pass.
+    if (tid == 0) scount = 0;
+    __syncthreads();
     for (int64_t eb = e0; eb < e1; eb += kBigBlock) {
       const int64_t e = eb + tid;
       bool cand = false;
@@ -1476,14 +1505,21 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
       if (m) {
         const int leader = __ffsll(static_cast<long long>(m)) - 1;
         int base = 0;
-        if (lane == leader) base = atomicAdd(&bi->cand_count, __popcll(m));
+        if (lane == leader) base = atomicAdd(&scount, __popcll(m));
         base = readlane_i32(base, leader);
-        if (cand) {
-          const int slot = base + __popcll(m & lanemask_lt());
-          if (slot < bi->cand_cap) fa.pool[bi->cand_off + slot] = static_cast<int32_t>(e - d.a);
-        }
+        // (at most kBigChunk candidates per chunk: the list always has room)
+        if (cand) slist[base + __popcll(m & lanemask_lt())] = static_cast<int32_t>(e - d.a);
       }
     }
+    __syncthreads();
+    const int nc = scount;
+    if (tid == 0 && nc > 0) sbase = atomicAdd(&bi->cand_count, nc);
+    __syncthreads();
+    for (int q = tid; q < nc; q += kBigBlock) {
+      const int slot = sbase + q;
+      if (slot < bi->cand_cap) fa.pool[bi->cand_off + slot] = slist[q];
+    }
+    __syncthreads();
   }
 }
 
