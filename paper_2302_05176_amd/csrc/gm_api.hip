@@ -15,7 +15,7 @@ hipError_t launch_plain(const SketchArgs& p, hipStream_t stream);
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
                          int republish, double seg_rest, int small_waves, int32_t* list,
                          void* plan, void* big, int32_t* pool, int64_t pool_cap,
-                         void* heavy, int64_t heavy_waves, int update, int cus,
+                         void* heavy, int64_t heavy_waves, void* part, int update, int cus,
                          unsigned long long* stats, hipStream_t stream);
 size_t plan_state_bytes();
 int64_t heavy_list_bytes();
@@ -23,6 +23,7 @@ void timing_enable(int level);
 int timing_collect(int n, char (*names)[64], double* ms, long long* launches);
 void timing_reset();
 size_t big_info_bytes();
+size_t part_scratch_bytes();
 hipError_t launch_jaccard(const int32_t* a, const int32_t* b, int64_t npairs, int32_t k,
                           double* out, hipStream_t stream);
 hipError_t launch_jaccard_pairs(const int32_t* store, int64_t nstore, int32_t k, const int64_t* ia,
@@ -55,6 +56,7 @@ struct PlanWorkspace {
   int32_t* pool = nullptr;
   void* heavy = nullptr;      // per-wave heavy-element lists of the FastGM walk
   int64_t heavy_waves = 0;
+  void* part = nullptr;       // partial sketches of split big-vector walks
 };
 
 // Resident waves per CU the heavy lists are sized for: the FastGM kernels
@@ -126,18 +128,34 @@ gm_status device_state(DeviceState** out) {
 gm_status plan_workspace(DeviceState* st, hipStream_t stream, int64_t nvec, PlanWorkspace** out) {
   std::lock_guard<std::mutex> lock(g_mu);
   PlanWorkspace& ws = st->plans[stream];
+  // each piece on its own, so that a call after a failed allocation retries
+  // what is missing
   if (!ws.plan) {
     hipError_t e = hipMalloc(&ws.plan, gm::plan_state_bytes());
-    if (e != hipSuccess) return from_hip(e);
+    if (e != hipSuccess) {
+      ws.plan = nullptr;
+      return from_hip(e);
+    }
+  }
+  if (!ws.pool) {
     void* q = nullptr;
-    e = hipMalloc(&q, sizeof(int32_t) * static_cast<size_t>(kPoolCap));
+    hipError_t e = hipMalloc(&q, sizeof(int32_t) * static_cast<size_t>(kPoolCap));
     if (e != hipSuccess) return from_hip(e);
     ws.pool = static_cast<int32_t*>(q);
+  }
+  if (!ws.heavy) {
+    void* q = nullptr;
     const int64_t waves = static_cast<int64_t>(st->cus) * kMaxWavesPerCu;
-    e = hipMalloc(&q, static_cast<size_t>(waves * gm::heavy_list_bytes()));
+    hipError_t e = hipMalloc(&q, static_cast<size_t>(waves * gm::heavy_list_bytes()));
     if (e != hipSuccess) return from_hip(e);
     ws.heavy = q;
     ws.heavy_waves = waves;
+  }
+  if (!ws.part) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, gm::part_scratch_bytes());
+    if (e != hipSuccess) return from_hip(e);
+    ws.part = q;
   }
   if (ws.cap < nvec) {
     if (ws.list) (void)hipFree(ws.list);
@@ -189,7 +207,7 @@ gm_status sketch_common(const int32_t* indices, const float* weights, const int6
   if (s != GM_OK) return s;
   return from_hip(gm::launch_fastgm(a, g_pos_bits, g_t0_scale, g_map_load, g_republish,
                                     g_seg_rest, g_small_waves, ws->list, ws->plan, ws->big,
-                                    ws->pool, kPoolCap, ws->heavy, ws->heavy_waves, update,
+                                    ws->pool, kPoolCap, ws->heavy, ws->heavy_waves, ws->part, update,
                                     st->cus, g_stats ? st->stats : nullptr, stream));
 }
 
@@ -408,6 +426,7 @@ void gm_release_stream(hipStream_t stream) {
   if (it->second.plan) (void)hipFree(it->second.plan);
   if (it->second.pool) (void)hipFree(it->second.pool);
   if (it->second.heavy) (void)hipFree(it->second.heavy);
+  if (it->second.part) (void)hipFree(it->second.part);
   st.plans.erase(it);
 }
 
@@ -429,6 +448,7 @@ void gm_release(void) {
       if (kv.second.plan) (void)hipFree(kv.second.plan);
       if (kv.second.pool) (void)hipFree(kv.second.pool);
       if (kv.second.heavy) (void)hipFree(kv.second.heavy);
+      if (kv.second.part) (void)hipFree(kv.second.part);
     }
     st.plans.clear();
   }

@@ -107,6 +107,7 @@ struct PlanState {
   int offset[kNumClasses];
   int next[kNumClasses];
   int64_t big_chunks;   // chunks of kBigChunk entries over all big vectors
+  int parts;            // walk tasks per big vector (1, or kMaxParts when few are big)
 };
 
 // Vectors above kLimM entries ("big") are prepared by two grid-wide passes
@@ -120,6 +121,19 @@ struct PlanState {
 // chunks of 8192).
 constexpr int64_t kBigChunk = 8192;
 
+// A call with at most kSplitMaxBig big vectors walks each one's candidate
+// list in up to kMaxParts parts (kPartCand candidates or more each), one
+// workgroup per part.  Each part sketches its share into a scratch area;
+// the last part to finish merges the partial sketches by the lexicographic
+// minimum (Sec. 2.3).  A part prunes at its own y*, which bounds every
+// register of the merged sketch, and walks up to T0 at most; so if no merged
+// register is empty, the merge is the sketch of the vector.  Otherwise the
+// last part walks the vector alone, as an unsplit vector is walked.
+constexpr int kMaxParts = 16;
+constexpr int kPartCand = 2048;
+constexpr int kSplitMaxBig = 16;
+constexpr int64_t kPartRegs = static_cast<int64_t>(kSplitMaxBig) * kMaxParts * GM_K_MAX;
+
 struct BigInfo {
   int64_t chunk_base;    // first chunk of this vector
   int64_t cand_off;      // offset of its candidate list in the pool
@@ -127,7 +141,8 @@ struct BigInfo {
   int bad;               // invalid entry seen
   int cand_count;        // candidates found (may exceed cand_cap)
   int cand_cap;          // room in the pool (0: no list, walk everything)
-  int pad;
+  int parts_done;        // parts of a split walk that have written their sketch
+  int64_t part_off;      // first scratch register of its parts (kMaxParts x k_max)
 };
 
 struct FastArgs {
@@ -149,6 +164,8 @@ struct FastArgs {
   int32_t update;       // 1: merge into the sketches already in out_idx/out_val
   int64_t wave_lim;     // vectors of at most this many entries: one wave each (0: none)
   int64_t heavy_waves;  // waves the heavy buffer has room for
+  int32_t* part_idx;    // partial sketches of split big vectors (kPartRegs registers)
+  double* part_val;
 };
 
 // Optional per-call counters (summed over the launch), indices:
@@ -918,6 +935,7 @@ struct FgShared {
   int contest;
   int bad;
   int task;
+  int last;         // this workgroup finished the last part of a split walk
   int hclaim;       // claim counter of the group's final heavy lists
   int hcount[16];   // records in each wave's final list
   int pclaim[16];   // each wave's own claim counter (lists walked alone)
@@ -945,12 +963,23 @@ __device__ __forceinline__ bool group_or(bool b) {
   }
 }
 
+// One part of a split walk (see kMaxParts): part `part` of `parts` walks
+// that share of the vector's candidate list into its scratch registers.
+struct PartTask {
+  int part, parts;
+};
+
 // Sketch vector v with a group of GW waves: the whole workgroup (GW = W) or
-// a single wave (GW = 1) with its own registers and shared words.
+// a single wave (GW = 1) with its own registers and shared words.  With a
+// part task, the workgroup sketches one part of a big vector and, if it is
+// the last part to finish, merges the parts into the output; it returns
+// true when the merged sketch has an empty register (the caller then walks
+// the vector unsplit).
 template <int GW, int G>
-__device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, FgShared& sh,
+__device__ bool sketch_vector(const FastArgs& fa, int64_t v, BigInfo* bi, FgShared& sh,
                               lds_u64* packed, lds_u64* fullkey, lds_u16* pm, int pm_stride,
-                              HeavyRec* hl, lds_u32* mp, const Queue& q) {
+                              HeavyRec* hl, lds_u32* mp, const Queue& q,
+                              const PartTask* pt = nullptr) {
   constexpr int kBlock = GW * kWave;
   const SketchArgs& p = fa.s;
   const int lane = threadIdx.x % kWave;
@@ -959,6 +988,10 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   const VecDesc d = vec_desc(p, v);
   const int32_t span = out_span(p, v, d);
   const int64_t n64 = d.b - d.a;
+  // where this sketch goes: the output, or a part's scratch registers
+  int32_t* const oidx = pt ? fa.part_idx : p.out_idx;
+  double* const oval = pt ? fa.part_val : p.out_val;
+  const int64_t obase = pt ? bi->part_off + static_cast<int64_t>(pt->part) * d.k : d.o;
   const bool bad0 = d.bad || n64 > 0x7FFFFFFF;
   // optional per-phase cycle accounting (statistics mode only)
   const bool timed = fa.stats != nullptr;
@@ -1039,7 +1072,7 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
     }
     if (bad && tid == 0) atomicAdd(p.err, 1ull);
     group_sync<GW>();
-    return;
+    return false;
   }
   // Update: the stored sketch is the sketch of the entries seen so far, so
   // an arrival above its largest register cannot change the merged result
@@ -1061,7 +1094,7 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
     if (lane == 0) sh.wmax[wave] = m;
     const bool any_poison = group_or<GW>(poisoned);  // also orders the wmax writes
     const bool any_empty = group_or<GW>(empty);
-    if (any_poison) return;  // a poisoned sketch stays poisoned
+    if (any_poison) return false;  // a poisoned sketch stays poisoned
     unsigned long long ms = 0;
     for (int qq = 0; qq < GW; ++qq) ms = sh.wmax[qq] > ms ? sh.wmax[qq] : ms;
     if (!any_empty) cap = bitsd(ms);
@@ -1076,6 +1109,12 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   if (bi && bi->cand_cap > 0 && bi->cand_count <= bi->cand_cap) {
     c.gather = fa.pool + bi->cand_off;
     c.n = bi->cand_count;
+    if (pt) {
+      const int lo = static_cast<int>(static_cast<int64_t>(bi->cand_count) * pt->part / pt->parts);
+      const int hi = static_cast<int>(static_cast<int64_t>(bi->cand_count) * (pt->part + 1) / pt->parts);
+      c.gather += lo;
+      c.n = hi - lo;
+    }
   }
   c.k = d.k;
   c.seed_mix = p.seed_mix;
@@ -1099,6 +1138,9 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
   // copy of the walk in the kernel.
   // big vectors keep the quantile their candidate lists were cut at
   double T = fmin(max_exp_quantile(d.k, bi ? 1e-4 : kFirstMiss) * fa.t0_scale / S, cap);
+  // a part leaves a register empty rather than walk further: the other
+  // parts may fill it
+  if (pt) cap = T;
   bool resolve = false;
   lds_i32* pclaim = (lds_i32*)(&sh.pclaim[wave]);
   lds_i32* hcount = (lds_i32*)(&sh.hcount[0]);
@@ -1183,14 +1225,43 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
           take = fk != kInfBits && (si < 0 || fk < sv || (fk == sv && oi[u] < si));
         }
         if (take) {
-          p.out_idx[d.o + j] = oi[u];
-          p.out_val[d.o + j] = bitsd(fk);
+          oidx[obase + j] = oi[u];
+          oval[obase + j] = bitsd(fk);
         }
       }
     }
   }
   group_sync<GW>();
   lap(kStCycOut);
+  if (!pt) return false;
+  // Publish this part's sketch; the last part to finish merges them all.
+  __threadfence();
+  group_sync<GW>();
+  if (tid == 0) sh.last = atomicAdd(&bi->parts_done, 1) == pt->parts - 1 ? 1 : 0;
+  group_sync<GW>();
+  if (!sh.last) return false;
+  __threadfence();
+  bool empty = false;
+  for (int j = tid; j < d.k; j += kBlock) {
+    int32_t wi = kIdxEmpty;
+    unsigned long long wv = kInfBits;
+    for (int qq = 0; qq < pt->parts; ++qq) {
+      const int64_t r = bi->part_off + static_cast<int64_t>(qq) * d.k + j;
+      const int32_t si = fa.part_idx[r];
+      const unsigned long long sv = dbits(fa.part_val[r]);
+      if (si >= 0 && (wi < 0 || sv < wv || (sv == wv && si < wi))) {
+        wi = si;
+        wv = sv;
+      }
+    }
+    if (wi < 0) {
+      empty = true;
+    } else {
+      p.out_idx[d.o + j] = wi;
+      p.out_val[d.o + j] = bitsd(wv);
+    }
+  }
+  return group_or<GW>(empty);
 }
 
 // Persistent kernel of one class: workgroups of W waves pull vector ids from
@@ -1198,10 +1269,11 @@ __device__ void sketch_vector(const FastArgs& fa, int64_t v, const BigInfo* bi, 
 // than fa.wave_lim is sketched by the whole workgroup; once the list reaches
 // vectors of at most fa.wave_lim entries, every wave takes vectors of its own
 // (with its own registers), so that the last large vectors overlap with the
-// small ones instead of leaving the other workgroups idle.
-template <int W, int G>
-__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(3)))
-void fastgm_class_kernel(FastArgs fa) {
+// small ones instead of leaving the other workgroups idle.  kSplit: the
+// classes of big vectors, whose walks may be split (see kMaxParts); they
+// have a kernel of their own, so that the other classes carry none of it.
+template <int W, int G, bool kSplit>
+__device__ __forceinline__ void class_body(const FastArgs& fa) {
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ FgShared sh[W];
   const int k_max = fa.lds_k;
@@ -1230,19 +1302,38 @@ void fastgm_class_kernel(FastArgs fa) {
   const int count = plan->count[fa.cls];
   const int32_t* list = fa.list + plan->offset[fa.cls];
   int* next = &fa.plan->next[fa.cls];
+  // big vectors: `parts` tasks each (parts of a split walk, see kMaxParts)
+  const bool bigc = fa.cls >= kBigFirst && fa.big;
+  const int parts = kSplit && bigc ? plan->parts : 1;
   int t = 0;
   for (;;) {
     if (threadIdx.x == 0) sh[0].task = atomicAdd(next, 1);
     __syncthreads();
     t = sh[0].task;
     __syncthreads();
-    if (t >= count) return;
-    const int64_t v = list[t];
+    if (t >= count * parts) return;
+    const int ti = t / parts;
+    const int part = t - ti * parts;
+    const int64_t v = list[ti];
     if (fa.wave_lim > 0 && fa.s.off[v + 1] - fa.s.off[v] <= fa.wave_lim) break;
-    const BigInfo* bi =
-        (fa.cls >= kBigFirst && fa.big) ? &fa.big[plan->offset[fa.cls] - plan->offset[kBigFirst] + t]
-                                        : nullptr;
-    sketch_vector<W, G>(fa, v, bi, sh[0], regs, regs + k_max, pm, pm_stride, hl, mp, q);
+    BigInfo* bi = bigc ? &fa.big[plan->offset[fa.cls] - plan->offset[kBigFirst] + ti] : nullptr;
+    int np = 1;
+    if (parts > 1 && !fa.update && !bi->bad && bi->S > 0.0 && bi->cand_cap > 0 &&
+        bi->cand_count <= bi->cand_cap) {
+      const int want = bi->cand_count / kPartCand;
+      np = want < 1 ? 1 : (want > parts ? parts : want);
+    }
+    if (part >= np) continue;
+    const PartTask pt{part, np};
+    // (one call site, so that the walk is inlined once; a split walk whose
+    // merge left a register empty is walked again, unsplit)
+    bool split = kSplit && np > 1;
+    for (;;) {
+      const bool redo = sketch_vector<W, G>(fa, v, bi, sh[0], regs, regs + k_max, pm, pm_stride, hl,
+                                            mp, q, split ? &pt : nullptr);
+      if (!redo) break;
+      split = false;
+    }
   }
   // one vector per wave from here on (wave 0 starts with the task in hand)
   lds_u64* wpacked = regs + 2 * k_max * wave;
@@ -1258,6 +1349,18 @@ void fastgm_class_kernel(FastArgs fa) {
                         hl, mp, q);
     mt = -1;
   }
+}
+
+template <int W, int G>
+__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(3)))
+void fastgm_class_kernel(FastArgs fa) {
+  class_body<W, G, false>(fa);
+}
+
+template <int W, int G>
+__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(3)))
+void fastgm_big_kernel(FastArgs fa) {
+  class_body<W, G, true>(fa);
 }
 
 // Planner: one workgroup sorts the vector ids by (size class, decreasing
@@ -1350,7 +1453,8 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t*
       bi.bad = 0;
       bi.cand_count = 0;
       bi.cand_cap = (bi.cand_off + cap <= pool_cap) ? static_cast<int>(cap) : 0;
-      bi.pad = 0;
+      bi.parts_done = 0;
+      bi.part_off = static_cast<int64_t>(i) * kMaxParts * GM_K_MAX;
       big[i] = bi;
     }
     __syncthreads();
@@ -1360,7 +1464,10 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t*
     }
     __syncthreads();
   }
-  if (tid == 0) plan->big_chunks = run_ch;
+  if (tid == 0) {
+    plan->big_chunks = run_ch;
+    plan->parts = c2 <= kSplitMaxBig ? kMaxParts : 1;
+  }
 }
 
 // Big vector owning chunk t (largest b with chunk_base <= t).
@@ -1651,7 +1758,9 @@ struct OccKey {
 template <int W, int G>
 static hipError_t launch_class(const FastArgs& fa, int cus, hipStream_t stream) {
   const size_t lds = fastgm_lds_bytes(fa.lds_k, W, fa.wave_lim > 0 ? W : 1);
-  const void* fn = reinterpret_cast<const void*>(fastgm_class_kernel<W, G>);
+  const bool big = fa.cls >= kBigFirst;
+  const void* fn = big ? reinterpret_cast<const void*>(fastgm_big_kernel<W, G>)
+                       : reinterpret_cast<const void*>(fastgm_class_kernel<W, G>);
   // occupancy per (kernel, LDS size), computed once
   static OccKey cache[64];
   static int ncache = 0;
@@ -1668,16 +1777,23 @@ static hipError_t launch_class(const FastArgs& fa, int cus, hipStream_t stream) 
     if (ncache < 64) cache[ncache++] = OccKey{fn, lds, per_cu};
   }
   int64_t grid = static_cast<int64_t>(cus) * per_cu;
-  if (grid > fa.s.nvec) grid = fa.s.nvec;
+  // tasks: one per vector, or up to kMaxParts per big vector
+  const int64_t tasks = fa.cls >= kBigFirst ? fa.s.nvec * kMaxParts : fa.s.nvec;
+  if (grid > tasks) grid = tasks;
   if (grid * W > fa.heavy_waves) grid = fa.heavy_waves / W;  // room in the heavy buffer
   if (grid < 1) return hipErrorInvalidValue;
   hipEvent_t ta = nullptr;
   // named as rocprofv3 names the kernel, plus the class it drains
   char name[64];
-  std::snprintf(name, sizeof(name), "fastgm_class_kernel<%d, %d> [class %d]", W, G, fa.cls);
+  std::snprintf(name, sizeof(name), "%s<%d, %d> [class %d]",
+                big ? "fastgm_big_kernel" : "fastgm_class_kernel", W, G, fa.cls);
   const int tid = timing_begin(name, true, stream, &ta);
-  hipLaunchKernelGGL((fastgm_class_kernel<W, G>), dim3(static_cast<unsigned>(grid)), dim3(W * kWave),
-                     lds, stream, fa);
+  if (big)
+    hipLaunchKernelGGL((fastgm_big_kernel<W, G>), dim3(static_cast<unsigned>(grid)), dim3(W * kWave),
+                       lds, stream, fa);
+  else
+    hipLaunchKernelGGL((fastgm_class_kernel<W, G>), dim3(static_cast<unsigned>(grid)),
+                       dim3(W * kWave), lds, stream, fa);
   timing_end(tid, ta, stream);
   return hipGetLastError();
 }
@@ -1699,10 +1815,12 @@ constexpr int64_t kLimM = 32768;
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
                          int republish, double seg_rest, int small_waves, int32_t* list,
                          void* plan, void* big, int32_t* pool, int64_t pool_cap,
-                         void* heavy, int64_t heavy_waves, int update, int cus,
+                         void* heavy, int64_t heavy_waves, void* part, int update, int cus,
                          unsigned long long* stats, hipStream_t stream) {
   FastArgs fa;
   fa.update = update;
+  fa.part_idx = static_cast<int32_t*>(part);
+  fa.part_val = reinterpret_cast<double*>(static_cast<char*>(part) + kPartRegs * sizeof(int32_t));
   fa.heavy = static_cast<HeavyRec*>(heavy);
   fa.heavy_waves = heavy_waves;
   fa.big = static_cast<BigInfo*>(big);
@@ -1757,5 +1875,8 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
 size_t plan_state_bytes() { return sizeof(PlanState); }
 int64_t heavy_list_bytes() { return kHeavyCapG * static_cast<int64_t>(sizeof(HeavyRec)); }
 size_t big_info_bytes() { return sizeof(BigInfo); }
+size_t part_scratch_bytes() {
+  return static_cast<size_t>(kPartRegs) * (sizeof(int32_t) + sizeof(double));
+}
 
 }  // namespace gm

@@ -304,6 +304,31 @@ def test_big_vectors_forced_paths(gm, opt, val):
         gm.reset_options()
 
 
+@pytest.mark.parametrize("t0_ppm", [1_000_000, 300_000])
+def test_big_vectors_split_walks(gm, t0_ppm):
+    """A call with few big vectors walks each candidate list in parts, one
+    workgroup each, and merges the partial sketches; with the threshold cut
+    to 0.3 T0 the merged sketch has empty registers and the vector is walked
+    again unsplit.  Both must give the oracle's sketch."""
+    idx, w, off = _big_batch(seed=7)
+    nvec = len(off) - 1
+    try:
+        gm.set_option("t0_scale_ppm", t0_ppm)
+        gm.set_option("stats", 1)
+        gm.reset_stats()
+        print(f"big vectors split t0_scale_ppm={t0_ppm}", flush=True)
+        got = _gpu_sketch(gm, idx, w, off, 1024, 23)
+        st = gm.get_stats()
+    finally:
+        gm.reset_options()
+    _assert_same(got, oracle.sketch(idx, w, off, 1024, 23, form=oracle.FORM_STREAM),
+                 f"t0_scale_ppm={t0_ppm}")
+    # more walks than vectors: the five big vectors were split into parts
+    assert st["vectors"] > nvec
+    if t0_ppm < 1_000_000:
+        assert st["passes"] > 0     # the unsplit walks had to widen the threshold
+
+
 def test_graph_capture_replays_match_eager(gm):
     """A FastGM batched call (planner, big-vector passes, class kernels)
     captured into a HIP graph gives the eager result on every replay, with
