@@ -1588,6 +1588,10 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
       __syncthreads();
     }
     const double c1 = 1.0 / static_cast<double>(d.k);
+    // The walk keeps an element when RN(O_1 RN(1/v)) <= T (T <= T0), which
+    // implies O_1 <= T0 v (1 + 2^-51.9); the test below, with two roundings
+    // of its own, admits at least that and needs no division.
+    const double bound = T0 * (1.0 + 0x1p-50);
     const int64_t e0 = d.a + (t - bi->chunk_base) * kBigChunk;
     const int64_t e1 = e0 + kBigChunk < d.b ? e0 + kBigChunk : d.b;
     // The chunk's candidates are gathered in LDS and the vector's list takes
@@ -1595,27 +1599,35 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
     // serialise the pass.
     if (tid == 0) scount = 0;
     __syncthreads();
-    for (int64_t eb = e0; eb < e1; eb += kBigBlock) {
-      const int64_t e = eb + tid;
-      bool cand = false;
-      if (e < e1) {
-        const float wv = p.w[e];
-        if (wv > 0.0f) {
-          const int32_t i = p.idx[e];
-          const uint64_t P = mix(p.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(i)));
-          const double r = 1.0 / static_cast<double>(wv);
-          const double O1 = fma(exp1(draw(P, kTagArrival, 1u)), c1, 0.0);
-          cand = O1 * r <= T0;
-        }
+    // four entries per lane per step, their loads issued together
+    constexpr int kPU = 4;
+    for (int64_t eb = e0; eb < e1; eb += kPU * kBigBlock) {
+      float wv[kPU];
+      int32_t iv[kPU];
+#pragma unroll
+      for (int u = 0; u < kPU; ++u) {
+        const int64_t e = eb + u * kBigBlock + tid;
+        wv[u] = e < e1 ? p.w[e] : 0.0f;
+        iv[u] = e < e1 ? p.idx[e] : 0;
       }
-      const uint64_t m = __ballot(cand);
-      if (m) {
-        const int leader = __ffsll(static_cast<long long>(m)) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&scount, __popcll(m));
-        base = readlane_i32(base, leader);
-        // (at most kBigChunk candidates per chunk: the list always has room)
-        if (cand) slist[base + __popcll(m & lanemask_lt())] = static_cast<int32_t>(e - d.a);
+#pragma unroll
+      for (int u = 0; u < kPU; ++u) {
+        const int64_t e = eb + u * kBigBlock + tid;
+        bool cand = false;
+        if (wv[u] > 0.0f) {
+          const uint64_t P = mix(p.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(iv[u])));
+          const double O1 = fma(exp1(draw(P, kTagArrival, 1u)), c1, 0.0);
+          cand = O1 <= bound * static_cast<double>(wv[u]);
+        }
+        const uint64_t m = __ballot(cand);
+        if (m) {
+          const int leader = __ffsll(static_cast<long long>(m)) - 1;
+          int base = 0;
+          if (lane == leader) base = atomicAdd(&scount, __popcll(m));
+          base = readlane_i32(base, leader);
+          // (at most kBigChunk candidates per chunk: the list always has room)
+          if (cand) slist[base + __popcll(m & lanemask_lt())] = static_cast<int32_t>(e - d.a);
+        }
       }
     }
     __syncthreads();
