@@ -1141,6 +1141,7 @@ __device__ bool sketch_vector(const FastArgs& fa, int64_t v, BigInfo* bi, FgShar
   // a part leaves a register empty rather than walk further: the other
   // parts may fill it
   if (pt) cap = T;
+  const double T_walk = T;  // the threshold every part walks to
   bool resolve = false;
   lds_i32* pclaim = (lds_i32*)(&sh.pclaim[wave]);
   lds_i32* hcount = (lds_i32*)(&sh.hcount[0]);
@@ -1218,8 +1219,9 @@ __device__ bool sketch_vector(const FastArgs& fa, int64_t v, BigInfo* bi, FgShar
       if (j < d.k) {
         const unsigned long long fk = fullkey[j];
         bool take = true;
-        if (fa.update) {
+        if (fa.update && !pt) {
           // lexicographic (value, index) minimum with the stored register
+          // (a part of a split walk leaves that to the merge)
           const int32_t si = p.out_idx[d.o + j];
           const unsigned long long sv = dbits(p.out_val[d.o + j]);
           take = fk != kInfBits && (si < 0 || fk < sv || (fk == sv && oi[u] < si));
@@ -1241,7 +1243,13 @@ __device__ bool sketch_vector(const FastArgs& fa, int64_t v, BigInfo* bi, FgShar
   group_sync<GW>();
   if (!sh.last) return false;
   __threadfence();
+  // A register is settled when a part filled it or, in an update, when the
+  // stored register lies within the parts' threshold T (no arrival above T
+  // was drawn, none at or below it was missed).  Merged registers written
+  // before an unsettled one sends the vector to the unsplit walk hold
+  // min(stored, new): walking the new entries again changes nothing more.
   bool empty = false;
+  const unsigned long long tb = dbits(T_walk);
   for (int j = tid; j < d.k; j += kBlock) {
     int32_t wi = kIdxEmpty;
     unsigned long long wv = kInfBits;
@@ -1254,7 +1262,17 @@ __device__ bool sketch_vector(const FastArgs& fa, int64_t v, BigInfo* bi, FgShar
         wv = sv;
       }
     }
-    if (wi < 0) {
+    bool settled = wi >= 0;
+    if (fa.update) {
+      const int32_t si = p.out_idx[d.o + j];
+      const unsigned long long sv = dbits(p.out_val[d.o + j]);
+      if (si >= 0 && sv <= tb) settled = true;
+      if (si >= 0 && (wi < 0 || sv < wv || (sv == wv && si < wi))) {
+        wi = si;
+        wv = sv;
+      }
+    }
+    if (!settled) {
       empty = true;
     } else {
       p.out_idx[d.o + j] = wi;
@@ -1318,7 +1336,7 @@ __device__ __forceinline__ void class_body(const FastArgs& fa) {
     if (fa.wave_lim > 0 && fa.s.off[v + 1] - fa.s.off[v] <= fa.wave_lim) break;
     BigInfo* bi = bigc ? &fa.big[plan->offset[fa.cls] - plan->offset[kBigFirst] + ti] : nullptr;
     int np = 1;
-    if (parts > 1 && !fa.update && !bi->bad && bi->S > 0.0 && bi->cand_cap > 0 &&
+    if (parts > 1 && !bi->bad && bi->S > 0.0 && bi->cand_cap > 0 &&
         bi->cand_count <= bi->cand_cap) {
       const int want = bi->cand_count / kPartCand;
       np = want < 1 ? 1 : (want > parts ? parts : want);

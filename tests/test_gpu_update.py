@@ -113,9 +113,19 @@ def test_repeats_empty_updates_and_poison(gm):
     torch.cuda.synchronize()
 
 
-def test_big_vector_updates(gm):
+@pytest.mark.parametrize("t0_ppm", [1_000_000, 300_000])
+def test_big_vector_updates(gm, t0_ppm):
+    """A big vector's chunks are walked in parts merged with the stored
+    sketch; at 0.3 T0 some registers stay unsettled and the update is walked
+    again unsplit."""
     idx, w, off = W.stream(nplus=120_000, seed=1205)
     k, seed = 1024, 2
     want = oracle.sketch(idx, w, off, k, seed, form=oracle.FORM_STREAM)
-    print("one 120k-entry vector in 2 chunks of ~60k (big-vector path)", flush=True)
-    _check(gm, _split(idx, w, off, 2, seed=3), k, seed, want, "big vector")
+    print(f"one 120k-entry vector in 2 chunks of ~60k (big-vector path), t0_scale_ppm={t0_ppm}",
+          flush=True)
+    try:
+        gm.set_option("t0_scale_ppm", t0_ppm)
+        _check(gm, _split(idx, w, off, 2, seed=3), k, seed, want, "big vector")
+        _check(gm, _split(idx, w, off, 3, seed=4), k, seed, want, "big vector, 3 chunks")
+    finally:
+        gm.reset_options()
