@@ -134,15 +134,21 @@ constexpr int kPartCand = 2048;
 constexpr int kSplitMaxBig = 16;
 constexpr int64_t kPartRegs = static_cast<int64_t>(kSplitMaxBig) * kMaxParts * GM_K_MAX;
 
+constexpr int kSumSlots = 16;  // partial sums of a big vector's weights
+
 struct BigInfo {
   int64_t chunk_base;    // first chunk of this vector
   int64_t cand_off;      // offset of its candidate list in the pool
-  double S;              // sum of weights (grid-wide atomic sum)
+  double S;              // sum of weights: the slots added in order (by the probe pass)
   int bad;               // invalid entry seen
   int cand_count;        // candidates found (may exceed cand_cap)
   int cand_cap;          // room in the pool (0: no list, walk everything)
   int parts_done;        // parts of a split walk that have written their sketch
   int64_t part_off;      // first scratch register of its parts (kMaxParts x k_max)
+  // chunk sums, added atomically into one of kSumSlots slots (one slot per
+  // chunk number mod kSumSlots: one address for every chunk would
+  // serialise the pass)
+  double Sslot[kSumSlots];
 };
 
 struct FastArgs {
@@ -1468,6 +1474,7 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t*
       bi.chunk_base = run_ch + sc_ch[tid] - nch;
       bi.cand_off = run_cap + sc_cap[tid] - cap;
       bi.S = 0.0;
+      for (int q = 0; q < kSumSlots; ++q) bi.Sslot[q] = 0.0;
       bi.bad = 0;
       bi.cand_count = 0;
       bi.cand_cap = (bi.cand_off + cap <= pool_cap) ? static_cast<int>(cap) : 0;
@@ -1522,8 +1529,8 @@ __global__ __launch_bounds__(kBigBlock) void big_sum_kernel(FastArgs fa) {
     if (tid == 0) sbad = 0;
     double part = 0.0;
     bool badl = false;
-    // eight independent loads per lane in flight per step
-    constexpr int kU = 8;
+    // sixteen independent loads per lane in flight per step
+    constexpr int kU = 16;
     int64_t e = e0 + tid;
     for (; e + (kU - 1) * kBigBlock < e1; e += kU * kBigBlock) {
       int32_t iv[kU];
@@ -1557,7 +1564,7 @@ __global__ __launch_bounds__(kBigBlock) void big_sum_kernel(FastArgs fa) {
     if (tid == 0) {
       double tot = 0.0;
       for (int q = 0; q < kBigBlock / kWave; ++q) tot += ws[q];
-      atomicAdd(&fa.big[b].S, tot);
+      atomicAdd(&fa.big[b].Sslot[t % kSumSlots], tot);
       if (sbad) atomicOr(&fa.big[b].bad, 1);
     }
     __syncthreads();
@@ -1580,8 +1587,12 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
     const int b = big_of_chunk(fa.big, c2, t);
     const VecDesc d = vec_desc(p, list2[b]);
     BigInfo* bi = &fa.big[b];
-    if (d.bad || bi->bad || !(bi->S > 0.0) || bi->cand_cap <= 0) continue;
-    double T0 = max_exp_quantile(d.k) * fa.t0_scale / bi->S;
+    double S = 0.0;
+    for (int q = 0; q < kSumSlots; ++q) S += bi->Sslot[q];
+    // (every block of the vector computes the same S; later launches read it)
+    if (tid == 0 && t == bi->chunk_base) bi->S = S;
+    if (d.bad || bi->bad || !(S > 0.0) || bi->cand_cap <= 0) continue;
+    double T0 = max_exp_quantile(d.k) * fa.t0_scale / S;
     if (fa.update) {
       // an update's walk stops at the stored sketch's largest register
       __shared__ unsigned long long smax[kBigBlock / kWave];
