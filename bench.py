@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -65,18 +66,25 @@ def harmonic(k: int) -> float:
 
 
 # Sources that build the measured sketch kernels or set their launch
-# parameters: a change to any of them makes committed counters stale.
+# parameters: a change to their code (comments and spacing aside) makes
+# committed counters stale.
 DIGEST_SOURCES = ["paper_2302_05176_amd/csrc/gm_fastgm.hip", "paper_2302_05176_amd/csrc/gm_plain.hip",
                   "paper_2302_05176_amd/csrc/gm_api.hip", "paper_2302_05176_amd/csrc/gm_common.h",
                   "paper_2302_05176_amd/csrc/gm_draw.h", "include/gm.h"]
 
 
+def _code_only(text: str) -> str:
+    text = re.sub(r"//[^\n]*", "", text)
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.sub(r"\s+", " ", text).strip()
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     for rel in DIGEST_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
+        with open(os.path.join(ROOT, rel)) as f:
             h.update(rel.encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 

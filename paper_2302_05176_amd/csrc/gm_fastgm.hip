@@ -23,14 +23,16 @@
 //    the packed prefix raise a per-vector "contest" flag, and the vector's
 //    indices are then resolved exactly by a second walk (see below).
 //  * Threshold: FastSearch's role (guess how far the queues must be released)
-//    is taken by a closed-form time threshold T0 = x_k / sum(v), x_k the
-//    (1 - 1e-4) quantile of the maximum of k Exp(1) variables (Sec. 2.5: the
-//    normalised y* is that maximum).  Each wave republishes
-//    T = min(T0, max_j y_j) every few iterations; registers only decrease, so
-//    any snapshot bounds the final y* from above and pruning stays exact.  If
-//    a register is still empty after the walk (probability 1e-4), the walk is
-//    repeated with a doubled threshold (the repeat re-emits the same
-//    arrivals, and a minimum does not care).
+//    is taken by a closed-form time threshold T0 = x_k / sum(v), x_k a high
+//    quantile of the maximum of k Exp(1) variables (Sec. 2.5: the normalised
+//    y* is that maximum): the 0.97 quantile for vectors walked over all their
+//    entries, 1 - 1e-4 for big vectors walked over candidate lists.  Each
+//    wave republishes T = min(T0, max_j y_j) every few iterations; registers
+//    only decrease, so any snapshot bounds the final y* from above and
+//    pruning stays exact.  If a register is still empty after the walk (3%
+//    of vectors, or 1e-4 of big ones), the walk is repeated with a doubled
+//    threshold (the repeat re-emits the same arrivals, and a minimum does
+//    not care).
 //  * Probe pass: 64 entries at a time (one per lane, loaded one pass ahead),
 //    every lane draws its element's first arrival; it is offered to its
 //    register, and an element whose first arrival is within T joins the

@@ -89,6 +89,11 @@ def test_options_validation(lib):
     assert lib.gm_set_option(99, 1) == N.GM_ERR_INVALID_ARG
     assert lib.gm_set_option(0, 24) == N.GM_OK
     assert lib.gm_set_option(3, 4) == N.GM_OK
+    # timing: 0 off, 1 every launch, 2 the sketch kernels only
+    assert lib.gm_set_option(7, 3) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_set_option(7, -1) == N.GM_ERR_INVALID_ARG
+    for level in (2, 1, 0):
+        assert lib.gm_set_option(7, level) == N.GM_OK
     assert lib.gm_status_string(1) == b"invalid argument"
 
 
