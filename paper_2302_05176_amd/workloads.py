@@ -211,3 +211,31 @@ def mixed(seed: int = 7, nvec: int = 64, dim: int = 1 << 20, max_n: int = 3000):
         rows_i.append(np.asarray(i, np.int64))
         rows_w.append(np.asarray(w, np.float32))
     return _pack(rows_i, rows_w)
+
+
+def sites(idx, w, off, nsites: int = 3, seed: int = 1020, reweight: bool = False):
+    """Spread every vector's entries over `nsites` overlapping sites: each entry
+    goes to a random non-empty subset of them.  With `reweight` each copy gets
+    its own weight (the entry's weight times a factor drawn from [0.25, 4)).
+
+    Returns two CSR triples: the site vectors (rows v*nsites .. v*nsites +
+    nsites - 1 belong to vector v) and the union vectors, which hold every
+    index of v once with the largest weight any site gives it."""
+    rng = _rng(seed)
+    site_i, site_w, uni_i, uni_w = [], [], [], []
+    for v in range(len(off) - 1):
+        ii = np.asarray(idx[off[v]:off[v + 1]])
+        ww = np.asarray(w[off[v]:off[v + 1]], np.float32)
+        mask = rng.integers(1, 1 << nsites, size=len(ii))
+        best = np.zeros(len(ii), np.float32)
+        for p in range(nsites):
+            sel = ((mask >> p) & 1) == 1
+            wp = ww[sel]
+            if reweight:
+                wp = (wp * rng.uniform(0.25, 4.0, size=wp.size)).astype(np.float32)
+            site_i.append(ii[sel])
+            site_w.append(wp)
+            best[sel] = np.maximum(best[sel], wp)
+        uni_i.append(ii)
+        uni_w.append(best)
+    return _pack(site_i, site_w), _pack(uni_i, uni_w)

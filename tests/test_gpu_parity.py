@@ -239,6 +239,29 @@ def test_merge_equals_sketch_of_union(gm):
     _assert_same((mi.cpu().numpy()[None], mv.cpu().numpy()[None]), whole, "merge")
 
 
+@pytest.mark.parametrize("reweight", [False, True])
+@pytest.mark.parametrize("k", [256, 1024])
+def test_merge_of_overlapping_sites(gm, k, reweight):
+    """Sec. 2.3 with sites whose sets overlap (and, with `reweight`, give an
+    element different weights): gm_merge of the sites' sketches equals the
+    sketch of the union vector.  The 100000-entry vector and its sites take
+    the big-vector path."""
+    sizes = np.array([100_000, 3, 40, 700, 2500, 9000, 120, 33_000])
+    idx, w, off = W.batch(nvec=len(sizes), seed=57, sizes=sizes)
+    (si, sw, so), (ui, uw, uo) = W.sites(idx, w, off, nsites=3, seed=58, reweight=reweight)
+    print(f"merge of overlapping sites k={k} reweight={reweight}", flush=True)
+    ps, py = _gpu_sketch(gm, si, sw, so, k, 21)
+    union = _gpu_sketch(gm, ui, uw, uo, k, 21)
+    _assert_same(union, oracle.sketch(ui, uw, uo, k, 21, form=oracle.FORM_STREAM), "union")
+    ps = torch.from_numpy(ps.reshape(len(sizes), 3, k)).to(DEV)
+    py = torch.from_numpy(py.reshape(len(sizes), 3, k)).to(DEV)
+    for v in range(len(sizes)):
+        mi, mv = gm.merge(ps[v], py[v])
+        torch.cuda.synchronize()
+        _assert_same((mi.cpu().numpy(), mv.cpu().numpy()), (union[0][v], union[1][v]),
+                     f"vector {v}")
+
+
 def test_order_and_duplicates_do_not_change_result(gm):
     idx, w, off = W.batch(nvec=20, seed=61)
     base = _gpu_sketch(gm, idx, w, off, 128, 6)

@@ -6,7 +6,10 @@ paper states hold bit-exactly.
 * A non-negative vector and its rescaling have the same sketch (Sec. 2.5):
   scaling by 2^m keeps indices and scales values by exactly 2^-m.
 * Mergeability (Sec. 2.3): sketch(A u B) == registerwise lexicographic min
-  of sketch(A) and sketch(B).
+  of sketch(A) and sketch(B), for disjoint parts and for sites whose sets
+  overlap.  An element's arrivals and permutation depend on its index only
+  and its keys fall as its weight grows, so when sites give one element
+  different weights the merge is the sketch of the largest.
 * Entry order and duplicated stream elements do not matter (Sec. 3).
 * The plain form's register j depends on (i, j) only, so a k-register plain
   sketch is the prefix of a larger one.
@@ -117,6 +120,32 @@ def test_split_and_merge(orc, form):
         ms = np.where(better, ps[:, part], ms)
     assert np.array_equal(ms, s)
     assert np.array_equal(_bits(my), _bits(y))
+
+
+def _merge_rows(s, y, nsites):
+    """Registerwise lexicographic (value, index) min over each group of rows."""
+    k = s.shape[1]
+    s = s.reshape(-1, nsites, k)
+    y = y.reshape(-1, nsites, k)
+    ms, my = s[:, 0].copy(), y[:, 0].copy()
+    for p in range(1, nsites):
+        better = (y[:, p] < my) | ((y[:, p] == my) & (s[:, p] < ms))
+        my = np.where(better, y[:, p], my)
+        ms = np.where(better, s[:, p], ms)
+    return ms, my
+
+
+@pytest.mark.parametrize("reweight", [False, True])
+@pytest.mark.parametrize("form", [0, 3])
+def test_merge_of_overlapping_sites(orc, form, reweight):
+    idx, w, off = W.batch(nvec=10, seed=43)
+    (si, sw, so), (ui, uw, uo) = W.sites(idx, w, off, nsites=3, seed=44, reweight=reweight)
+    k = 64
+    union = orc.sketch(ui, uw, uo, k, 12, form=form)
+    merged = _merge_rows(*orc.sketch(si, sw, so, k, 12, form=form), 3)
+    assert _same(merged, union)
+    if not reweight:
+        assert _same(union, orc.sketch(idx, w, off, k, 12, form=form))
 
 
 @pytest.mark.parametrize("form", [0, 1, 3])
