@@ -67,18 +67,28 @@ def make_trace(nreq: int, rate: float, nstore: int, seed: int = 1005, sketch_eve
     return reqs, idx, w
 
 
-def build_store(nstore: int, k: int, seed: int = 1006, nplus: int = 32, chunk: int = 200_000,
-                device="cuda:0"):
-    """Device [nstore, k] int32 store: FastGM sketches of seeded vectors with
-    nplus distinct indices each."""
-    import torch
-    from . import sketch
+def store_vectors(nstore: int, seed: int = 1006, nplus: int = 32, chunk: int = 200_000):
+    """The store's seeded vectors, chunk by chunk: yields (first row, idx
+    [m, nplus] int32, w [m, nplus] float32).  Indices are uniform in
+    [0, 2^24) (a repeat inside a row is one element at its largest weight);
+    weights are Exp(1) + 1e-6."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    store = torch.empty((nstore, k), dtype=torch.int32, device=device)
     for s0 in range(0, nstore, chunk):
         m = min(chunk, nstore - s0)
         idx = rng.integers(0, 1 << 24, size=(m, nplus), dtype=np.int64).astype(np.int32)
         w = rng.exponential(1.0, size=(m, nplus)).astype(np.float32) + np.float32(1e-6)
+        yield s0, idx, w
+
+
+def build_store(nstore: int, k: int, seed: int = 1006, nplus: int = 32, chunk: int = 200_000,
+                device="cuda:0"):
+    """Device [nstore, k] int32 store: FastGM sketches (sketch seed `seed`) of
+    the vectors store_vectors(nstore, seed, nplus, chunk) yields."""
+    import torch
+    from . import sketch
+    store = torch.empty((nstore, k), dtype=torch.int32, device=device)
+    for s0, idx, w in store_vectors(nstore, seed, nplus, chunk):
+        m = idx.shape[0]
         off = np.arange(m + 1, dtype=np.int64) * nplus
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to(device)
         sketch(t(idx), t(w), t(off), k, seed, out_idx=store[s0:s0 + m])

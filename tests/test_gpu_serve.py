@@ -11,6 +11,20 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+def oracle_store(nstore, k, rows=None, seed=1006, nplus=32):
+    """The oracle's sketches (indices) of the store's seeded vectors, for the
+    given rows (all when None); a dictionary row -> indices when rows are
+    given."""
+    from paper_2302_05176_amd import serve
+    parts = list(serve.store_vectors(nstore, seed, nplus))
+    vi = np.concatenate([c[1] for c in parts])
+    vw = np.concatenate([c[2] for c in parts])
+    sel = np.arange(nstore) if rows is None else np.unique(np.asarray(rows, np.int64))
+    off = np.arange(len(sel) + 1, dtype=np.int64) * nplus
+    s, _ = oracle.sketch(vi[sel].reshape(-1), vw[sel].reshape(-1), off, k, seed)
+    return s if rows is None else {int(r): s[i] for i, r in enumerate(sel)}
+
+
 def test_serving_results_same_alone_and_in_the_mix():
     import paper_2302_05176_amd as gm
     from paper_2302_05176_amd import serve
@@ -39,10 +53,11 @@ def test_serving_results_same_alone_and_in_the_mix():
         a, b = int(reqs["a"][r]), int(reqs["b"][r])
         os_, oy = oracle.sketch(hi[a:b], hw[a:b], np.array([0, b - a]), k, 7)
         assert np.array_equal(os_[0], res["sketch_idx"][row])
-    st_h = store.cpu().numpy()
+    # Jaccard answers against the oracle's sketches of the stored vectors
+    want_store = oracle_store(nstore, k)
     jq = np.nonzero(reqs["kind"] == serve.JACCARD)[0]
     for r in jq:
-        want = oracle.jaccard(st_h[reqs["a"][r]], st_h[reqs["b"][r]])
+        want = oracle.jaccard(want_store[reqs["a"][r]], want_store[reqs["b"][r]])
         assert res["jaccard"][r] == want, f"query {r}"
     summ = serve.summarize(reqs, res)
     assert summ["p99_us"] >= summ["p50_us"] > 0
