@@ -212,10 +212,12 @@ def test_estimators_match_oracle(gm):
     a = torch.from_numpy(s[0::2].copy()).to(DEV)
     b = torch.from_numpy(s[1::2].copy()).to(DEV)
     J = gm.jaccard_est(a, b).cpu().numpy()
-    Jo = np.array([oracle.jaccard(s[2 * p], s[2 * p + 1]) for p in range(200)])
+    # end to end on each side: the oracle's estimates of the oracle's sketches
+    os_, oy = oracle.sketch(idx, w, off, k, 2, form=oracle.FORM_STREAM)
+    Jo = np.array([oracle.jaccard(os_[2 * p], os_[2 * p + 1]) for p in range(200)])
     assert np.array_equal(J.view(np.uint64), Jo.view(np.uint64))
     C = gm.wcard_est(torch.from_numpy(y).to(DEV)).cpu().numpy()
-    Co = np.array([oracle.wcard(y[v]) for v in range(len(y))])
+    Co = np.array([oracle.wcard(oy[v]) for v in range(len(oy))])
     assert np.array_equal(C.view(np.uint64), Co.view(np.uint64))
     # store lookups, including out-of-range rows
     store = torch.from_numpy(s).to(DEV)
