@@ -521,13 +521,23 @@ def bench_serve(args):
     t0 = time.perf_counter()
     store = serve.build_store(nstore, k)
     build_s = time.perf_counter() - t0
+    # 8 slots, no batching window: a free slot takes what is pending at once
+    cfg = dict(slots=8, max_batch_requests=256, max_wait_us=0.0, device_budget_bytes=4 << 30)
     reqs, hi, hw = serve.make_trace(20_000, rate=20_000.0, nstore=nstore)
-    res = serve.run(reqs, hi, hw, store, k, seed=args.seed, slots=4, max_batch_requests=256,
-                    max_wait_us=200.0, device_budget_bytes=4 << 30)
+    res = serve.run(reqs, hi, hw, store, k, seed=args.seed, **cfg)
     summ = serve.summarize(reqs, res)
+    # toward saturation: 2x, 5x and 10x the arrival rate
+    sweep = []
+    for mult in (2, 5, 10):
+        rq, rhi, rhw = serve.make_trace(40_000, rate=20_000.0 * mult, nstore=nstore)
+        r2 = serve.run(rq, rhi, rhw, store, k, seed=args.seed, **cfg)
+        sweep.append({"rate_req_s": 20_000.0 * mult, **serve.summarize(rq, r2),
+                      "batches": r2["stats"]["batches"]})
     print(json.dumps({"workload": "serving: Poisson 20,000 req/s, 1 sketch (k=512, n+ ~ "
-                                  "lognormal(ln 2000, 1.5)) per 4 Jaccard queries on 1e6 stored sketches",
+                                  "lognormal(ln 2000, 1.5) clipped to [10, 1e6]) per 4 Jaccard "
+                                  "queries on 1e6 stored sketches",
                       "requests": len(reqs), "summary": summ, "stats": res["stats"],
+                      "config": cfg, "saturation": sweep,
                       "store_build_s": build_s}), flush=True)
 
 

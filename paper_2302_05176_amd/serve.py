@@ -40,7 +40,7 @@ class ServeStats(ctypes.Structure):
 
 def make_trace(nreq: int, rate: float, nstore: int, seed: int = 1005, sketch_every: int = 5,
                size_mu: float = float(np.log(2000.0)), size_sigma: float = 1.5,
-               size_cap: int = 100_000, dim: int = 1 << 24):
+               size_cap: int = 1_000_000, dim: int = 1 << 24):
     """Returns (reqs structured array, host_idx int32, host_w float32)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     gaps = rng.exponential(1e6 / rate, size=nreq)
@@ -96,11 +96,16 @@ def build_store(nstore: int, k: int, seed: int = 1006, nplus: int = 32, chunk: i
     return store
 
 
-def run(reqs, host_idx, host_w, store, k: int, seed: int = 1, slots: int = 4,
+def run(reqs, host_idx, host_w, store, k: int, seed: int = 1, slots: int = 8,
         max_batch_requests: int = 256, max_batch_entries: int | None = None,
-        device_budget_bytes: int = 1 << 30, max_wait_us: float = 200.0, realtime: bool = True,
+        device_budget_bytes: int = 1 << 30, max_wait_us: float = 0.0, realtime: bool = True,
         want_sketches: bool = False):
-    """Run the native loop; returns a dict of per-request arrays and stats."""
+    """Run the native loop; returns a dict of per-request arrays and stats.
+
+    With max_wait_us = 0 a free slot takes whatever is pending at once; while
+    every slot is busy, arrivals accumulate and the next free slot takes them
+    as one batch.  A positive max_wait_us holds a partial batch until its
+    oldest request has waited that long."""
     import torch
     L = _native.load()
     nreq = len(reqs)

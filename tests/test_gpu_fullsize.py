@@ -178,8 +178,8 @@ def test_serving_full_sampled(gm):
     store = serve.build_store(nstore, k)
     reqs, hi, hw = serve.make_trace(20_000, rate=20_000.0, nstore=nstore)
     print("serving: 20,000 requests", flush=True)
-    res = serve.run(reqs, hi, hw, store, k, seed=seed, slots=4, max_batch_requests=256,
-                    max_wait_us=200.0, device_budget_bytes=4 << 30, want_sketches=True)
+    res = serve.run(reqs, hi, hw, store, k, seed=seed, slots=8, max_batch_requests=256,
+                    max_wait_us=0.0, device_budget_bytes=4 << 30, want_sketches=True)
     st = res["stats"]
     assert st["sketch_requests"] + st["jaccard_requests"] == len(reqs)
     assert np.all(res["latency_us"] > 0)
@@ -198,7 +198,9 @@ def test_serving_full_sampled(gm):
         assert np.array_equal(got[i], want_rows[r]), f"stored row {r}"
     # sampled sketch requests
     sk = np.nonzero(reqs["kind"] == serve.SKETCH)[0]
-    for row in rng.choice(len(sk), 40, replace=False):
+    sizes = reqs["b"][sk] - reqs["a"][sk]
+    # 40 sampled sketch requests and the largest (big-vector passes)
+    for row in set(rng.choice(len(sk), 40, replace=False).tolist()) | {int(np.argmax(sizes))}:
         r = sk[row]
         a, b = int(reqs["a"][r]), int(reqs["b"][r])
         ws, wy = oracle.sketch(hi[a:b], hw[a:b], np.array([0, b - a]), k, seed)
