@@ -348,7 +348,9 @@ gm_status gm_autotune(const int32_t *indices, const float *weights, const int64_
  * a free slot admits pending requests in arrival order while the batch holds
  * at most max_batch_requests requests and max_batch_entries sketch entries
  * and the in-flight device bytes stay within device_budget_bytes; a partial
- * batch waits for more requests until its oldest one has waited max_wait_us.
+ * batch waits for more requests until its oldest one has waited max_wait_us
+ * (0: it launches at once; while every slot is busy, arrivals accumulate and
+ * the next free slot takes them together).
  *   host_idx/host_w   host CSR entries of the sketch requests (request r
  *                     sketches entries [a, b); b - a <= max_batch_entries)
  *   store_idx         device [nstore * k] int32 sketch indices; a Jaccard
