@@ -1331,12 +1331,25 @@ __device__ __forceinline__ void class_body(const FastArgs& fa) {
   // big vectors: `parts` tasks each (parts of a split walk, see kMaxParts)
   const bool bigc = fa.cls >= kBigFirst && fa.big;
   const int parts = kSplit && bigc ? plan->parts : 1;
+  // Tasks b*W .. b*W + W - 1 belong to workgroup b from the start (the
+  // list is sorted, so they are the largest vectors); the class counter
+  // hands out the rest, from gridDim.x * W on.  Without the static share
+  // every wave of the grid would claim its first task from the one counter
+  // at the same moment, and those device-scope atomics serialise.
+  const int nstatic = static_cast<int>(gridDim.x) * W;
+  int used = 0;  // static tasks of this workgroup taken so far
   int t = 0;
   for (;;) {
-    if (threadIdx.x == 0) sh[0].task = atomicAdd(next, 1);
-    __syncthreads();
-    t = sh[0].task;
-    __syncthreads();
+    if (used < W) {
+      t = static_cast<int>(blockIdx.x) * W + used;
+      ++used;
+      __syncthreads();  // the previous vector's last reads of the shared state
+    } else {
+      if (threadIdx.x == 0) sh[0].task = nstatic + atomicAdd(next, 1);
+      __syncthreads();
+      t = sh[0].task;
+      __syncthreads();
+    }
     if (t >= count * parts) return;
     const int ti = t / parts;
     const int part = t - ti * parts;
@@ -1361,13 +1374,15 @@ __device__ __forceinline__ void class_body(const FastArgs& fa) {
       split = false;
     }
   }
-  // one vector per wave from here on (wave 0 starts with the task in hand)
+  // one vector per wave from here on: wave 0 starts with the task in hand,
+  // waves 1.. with the workgroup's remaining static tasks, if any
   lds_u64* wpacked = regs + 2 * k_max * wave;
-  int mt = wave == 0 ? t : -1;
+  const int si = used + wave - 1;
+  int mt = wave == 0 ? t : (si < W ? static_cast<int>(blockIdx.x) * W + si : -1);
   for (;;) {
     if (mt < 0) {
       int got = 0;
-      if (lane == 0) got = atomicAdd(next, 1);
+      if (lane == 0) got = nstatic + atomicAdd(next, 1);
       mt = readlane_i32(got, 0);
     }
     if (mt >= count) break;
