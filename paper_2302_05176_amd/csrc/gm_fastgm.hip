@@ -1331,17 +1331,19 @@ __device__ __forceinline__ void class_body(const FastArgs& fa) {
   // big vectors: `parts` tasks each (parts of a split walk, see kMaxParts)
   const bool bigc = fa.cls >= kBigFirst && fa.big;
   const int parts = kSplit && bigc ? plan->parts : 1;
-  // Tasks b*W .. b*W + W - 1 belong to workgroup b from the start (the
-  // list is sorted, so they are the largest vectors); the class counter
-  // hands out the rest, from gridDim.x * W on.  Without the static share
-  // every wave of the grid would claim its first task from the one counter
-  // at the same moment, and those device-scope atomics serialise.
-  const int nstatic = static_cast<int>(gridDim.x) * W;
+  // Tasks b, b + n, .., b + (W - 1) n (n workgroups) belong to workgroup b
+  // from the start: each of the first W rounds of the sorted list gives
+  // every workgroup one task, largest first, as the counter would.  The
+  // class counter hands out the rest, from n W on.  Without the static
+  // share every wave of the grid would claim its first task from the one
+  // counter at the same moment, and those device-scope atomics serialise.
+  const int ngroups = static_cast<int>(gridDim.x);
+  const int nstatic = ngroups * W;
   int used = 0;  // static tasks of this workgroup taken so far
   int t = 0;
   for (;;) {
     if (used < W) {
-      t = static_cast<int>(blockIdx.x) * W + used;
+      t = static_cast<int>(blockIdx.x) + used * ngroups;
       ++used;
       __syncthreads();  // the previous vector's last reads of the shared state
     } else {
@@ -1378,7 +1380,7 @@ __device__ __forceinline__ void class_body(const FastArgs& fa) {
   // waves 1.. with the workgroup's remaining static tasks, if any
   lds_u64* wpacked = regs + 2 * k_max * wave;
   const int si = used + wave - 1;
-  int mt = wave == 0 ? t : (si < W ? static_cast<int>(blockIdx.x) * W + si : -1);
+  int mt = wave == 0 ? t : (si < W ? static_cast<int>(blockIdx.x) + si * ngroups : -1);
   for (;;) {
     if (mt < 0) {
       int got = 0;
