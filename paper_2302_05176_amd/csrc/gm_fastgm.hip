@@ -381,12 +381,44 @@ __device__ __forceinline__ void fy_step_flat(int32_t j, uint32_t& cval, uint32_t
   after = (after << 1) & after;
 }
 
+// A flat batch of a 64-lane segment without the sweep.  Only duplicate
+// targets interact there: a lane takes the displaced value of the last
+// earlier lane with its target, and its own write stands only if no later
+// lane has that target.  The lanes sharing each lane's target come from one
+// ballot per bit of the (1-based, at most GM_K_MAX) target, all independent,
+// where the sweep takes 64 dependent steps.  Lanes past the segment's stop
+// carry negative targets and match nothing.
+constexpr int kTargetBits = 13;
+static_assert(GM_K_MAX < (1 << kTargetBits), "targets must fit the ballot bits");
+
+__device__ __forceinline__ bool fy_flat64(int32_t j, uint32_t& cval, uint32_t disp) {
+  const uint32_t lane = __lane_id();
+  uint64_t same = __ballot(j >= 0);
+#pragma unroll
+  for (int b = 0; b < kTargetBits; ++b) {
+    const bool bit = ((j >> b) & 1) != 0;
+    const uint64_t m = __ballot(bit);
+    same &= bit ? m : ~m;
+  }
+  if (j < 0) same = 0;
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint64_t earlier = same & below;
+  const uint64_t later = same & ~below & ~(1ull << lane);
+  const int src = earlier ? 63 - __clzll(static_cast<long long>(earlier)) : static_cast<int>(lane);
+  const uint32_t dl = static_cast<uint32_t>(__shfl(static_cast<int>(disp), src));
+  if (earlier) cval = dl;
+  return later != 0;
+}
+
 // `inwin`: some lane of the wave swaps with a position of its own batch
 // beyond its step (z_L < j_L <= the batch's last step), so that a later
 // step's displaced value changes during the batch.
 template <int G, int... Ls>
 __device__ __forceinline__ bool fy_batch(std::integer_sequence<int, Ls...>, int32_t j, int32_t z,
                                          bool inwin, uint32_t& cval, uint32_t& disp) {
+  if constexpr (G == 64) {
+    if (!inwin) return fy_flat64(j, cval, disp);
+  }
   uint64_t after = ~seg_first_lanes<G>(), before = 0, killm = 0;
   // computed step by step with two scalar operations each: folded to
   // constants, the masks of all steps would be hoisted and held in scalar
