@@ -381,26 +381,30 @@ __device__ __forceinline__ void fy_step_flat(int32_t j, uint32_t& cval, uint32_t
   after = (after << 1) & after;
 }
 
-// A flat batch of a 64-lane segment without the sweep.  Only duplicate
-// targets interact there: a lane takes the displaced value of the last
-// earlier lane with its target, and its own write stands only if no later
-// lane has that target.  The lanes sharing each lane's target come from one
-// ballot per bit of the (1-based, at most GM_K_MAX) target, all independent,
-// where the sweep takes 64 dependent steps.  Lanes past the segment's stop
-// carry negative targets and match nothing.
-constexpr int kTargetBits = 13;
-static_assert(GM_K_MAX < (1 << kTargetBits), "targets must fit the ballot bits");
+// A flat batch without the sweep.  Only duplicate targets interact there:
+// a lane takes the displaced value of the last earlier lane of its segment
+// with its target, and its own write stands only if no later lane of the
+// segment has that target.  The lanes sharing each lane's target come from
+// one ballot per bit of the (1-based) target, all independent, where the
+// sweep takes G dependent steps.  A G-lane segment serves k up to
+// segment_lanes' bound for G, so its targets fit target_bits<G>() bits.
+// Lanes past the segment's stop carry negative targets and match nothing.
+template <int G>
+__host__ __device__ constexpr int target_bits() { return G == 8 ? 9 : (G == 16 ? 11 : 13); }
+static_assert(GM_K_MAX < (1 << target_bits<64>()), "targets must fit the ballot bits");
 
-__device__ __forceinline__ bool fy_flat64(int32_t j, uint32_t& cval, uint32_t disp) {
+template <int G>
+__device__ __forceinline__ bool fy_flat(int32_t j, uint32_t& cval, uint32_t disp) {
   const uint32_t lane = __lane_id();
   uint64_t same = __ballot(j >= 0);
 #pragma unroll
-  for (int b = 0; b < kTargetBits; ++b) {
+  for (int b = 0; b < target_bits<G>(); ++b) {
     const bool bit = ((j >> b) & 1) != 0;
     const uint64_t m = __ballot(bit);
     same &= bit ? m : ~m;
   }
   if (j < 0) same = 0;
+  if constexpr (G < 64) same &= ((1ull << G) - 1ull) << (lane & ~static_cast<uint32_t>(G - 1));
   const uint64_t below = (1ull << lane) - 1ull;
   const uint64_t earlier = same & below;
   const uint64_t later = same & ~below & ~(1ull << lane);
@@ -416,9 +420,7 @@ __device__ __forceinline__ bool fy_flat64(int32_t j, uint32_t& cval, uint32_t di
 template <int G, int... Ls>
 __device__ __forceinline__ bool fy_batch(std::integer_sequence<int, Ls...>, int32_t j, int32_t z,
                                          bool inwin, uint32_t& cval, uint32_t& disp) {
-  if constexpr (G == 64) {
-    if (!inwin) return fy_flat64(j, cval, disp);
-  }
+  if (!inwin) return fy_flat<G>(j, cval, disp);
   uint64_t after = ~seg_first_lanes<G>(), before = 0, killm = 0;
   // computed step by step with two scalar operations each: folded to
   // constants, the masks of all steps would be hoisted and held in scalar
@@ -948,6 +950,11 @@ __host__ __device__ constexpr int perm_stride(int k_max) { return ((k_max + 1 + 
 __host__ __device__ constexpr int segment_lanes(int k_max) {
   return k_max <= 256 ? 8 : (k_max <= 1024 ? 16 : 64);
 }
+// the flat resolution's ballots cover every target of the k a width serves
+static_assert(segment_lanes(256) == 8 && segment_lanes(257) == 16 &&
+                  256 < (1 << target_bits<8>()), "8-lane targets");
+static_assert(segment_lanes(1024) == 16 && segment_lanes(1025) == 64 &&
+                  1024 < (1 << target_bits<16>()), "16-lane targets");
 
 __host__ __device__ constexpr size_t light_lds_bytes() {
   return queue_bytes() + static_cast<size_t>(kMapSlots) * kWave * 4;
