@@ -420,7 +420,11 @@ __device__ __forceinline__ bool fy_flat(int32_t j, uint32_t& cval, uint32_t disp
 template <int G, int... Ls>
 __device__ __forceinline__ bool fy_batch(std::integer_sequence<int, Ls...>, int32_t j, int32_t z,
                                          bool inwin, uint32_t& cval, uint32_t& disp) {
-  if (!inwin) return fy_flat<G>(j, cval, disp);
+  // (64-lane segments only: for 8 and 16 lanes the sweep is a few row
+  // broadcasts, and the ballots' registers spill there)
+  if constexpr (G == 64) {
+    if (!inwin) return fy_flat<G>(j, cval, disp);
+  }
   uint64_t after = ~seg_first_lanes<G>(), before = 0, killm = 0;
   // computed step by step with two scalar operations each: folded to
   // constants, the masks of all steps would be hoisted and held in scalar
