@@ -381,31 +381,49 @@ __device__ __forceinline__ void fy_step_flat(int32_t j, uint32_t& cval, uint32_t
   after = (after << 1) & after;
 }
 
-// A flat batch without the sweep.  Only duplicate targets interact there:
-// a lane takes the displaced value of the last earlier lane of its segment
-// with its target, and its own write stands only if no later lane of the
-// segment has that target.  The lanes sharing each lane's target come from
-// one ballot per bit of the (1-based) target, all independent, where the
-// sweep takes G dependent steps.  A G-lane segment serves k up to
-// segment_lanes' bound for G, so its targets fit target_bits<G>() bits.
-// Lanes past the segment's stop carry negative targets and match nothing.
-template <int G>
-__host__ __device__ constexpr int target_bits() { return G == 8 ? 9 : (G == 16 ? 11 : 13); }
-static_assert(GM_K_MAX < (1 << target_bits<64>()), "targets must fit the ballot bits");
+// A batch of a 64-lane segment without the sweep.  Step L of the sweep
+// swaps positions z_L and j_L, so three rules make it up:
+// * a lane whose own position z is the target of earlier lanes takes, as
+//   its displaced value, that of the last of them (itself resolved the same
+//   way: the chain runs to ever earlier lanes);
+// * a lane's server is the displaced value of the last earlier lane with
+//   its target, else what it read at its target;
+// * a lane's write stands only if no later lane has its target.
+// One ballot per bit of the (1-based, at most GM_K_MAX) targets gives every
+// lane the lanes whose target equals its own target and those whose target
+// equals its position; the chains are followed by pointer jumping, at most
+// six rounds for 64 lanes (none when no lane targets a position in its own
+// batch).  Lanes past the segment's stop carry negative targets and match
+// nothing.
+constexpr int kTargetBits = 13;
+static_assert(GM_K_MAX < (1 << kTargetBits), "targets must fit the ballot bits");
 
-template <int G>
-__device__ __forceinline__ bool fy_flat(int32_t j, uint32_t& cval, uint32_t disp) {
+__device__ __forceinline__ bool fy_resolve64(int32_t j, int32_t z, uint32_t& cval, uint32_t& disp) {
   const uint32_t lane = __lane_id();
-  uint64_t same = __ballot(j >= 0);
+  const uint64_t valid = __ballot(j >= 0);
+  uint64_t same = valid, at_z = valid;
 #pragma unroll
-  for (int b = 0; b < target_bits<G>(); ++b) {
-    const bool bit = ((j >> b) & 1) != 0;
-    const uint64_t m = __ballot(bit);
-    same &= bit ? m : ~m;
+  for (int b = 0; b < kTargetBits; ++b) {
+    const uint64_t m = __ballot(((j >> b) & 1) != 0);
+    same &= ((j >> b) & 1) ? m : ~m;
+    at_z &= ((z >> b) & 1) ? m : ~m;
   }
   if (j < 0) same = 0;
-  if constexpr (G < 64) same &= ((1ull << G) - 1ull) << (lane & ~static_cast<uint32_t>(G - 1));
   const uint64_t below = (1ull << lane) - 1ull;
+  // displaced values along the chains of earlier lanes targeting z
+  const uint64_t zsrc = at_z & below;
+  int ptr = zsrc ? 63 - __clzll(static_cast<long long>(zsrc)) : -1;
+  uint32_t val = disp;
+  while (__ballot(ptr >= 0) != 0) {
+    const int from = ptr >= 0 ? ptr : static_cast<int>(lane);
+    const uint32_t v2 = static_cast<uint32_t>(__shfl(static_cast<int>(val), from));
+    const int p2 = __shfl(ptr, from);
+    if (ptr >= 0) {
+      val = v2;
+      ptr = p2;
+    }
+  }
+  disp = val;
   const uint64_t earlier = same & below;
   const uint64_t later = same & ~below & ~(1ull << lane);
   const int src = earlier ? 63 - __clzll(static_cast<long long>(earlier)) : static_cast<int>(lane);
@@ -423,18 +441,20 @@ __device__ __forceinline__ bool fy_batch(std::integer_sequence<int, Ls...>, int3
   // (64-lane segments only: for 8 and 16 lanes the sweep is a few row
   // broadcasts, and the ballots' registers spill there)
   if constexpr (G == 64) {
-    if (!inwin) return fy_flat<G>(j, cval, disp);
+    (void)inwin;
+    return fy_resolve64(j, z, cval, disp);
+  } else {
+    uint64_t after = ~seg_first_lanes<G>(), before = 0, killm = 0;
+    // computed step by step with two scalar operations each: folded to
+    // constants, the masks of all steps would be hoisted and held in scalar
+    // registers across the whole walk
+    asm volatile("" : "+s"(after), "+s"(before));
+    if (inwin)
+      (fy_step<G, Ls>(j, z, cval, disp, after, before, killm), ...);
+    else
+      (fy_step_flat<G, Ls>(j, cval, disp, after, before, killm), ...);
+    return __builtin_amdgcn_inverse_ballot_w64(killm);
   }
-  uint64_t after = ~seg_first_lanes<G>(), before = 0, killm = 0;
-  // computed step by step with two scalar operations each: folded to
-  // constants, the masks of all steps would be hoisted and held in scalar
-  // registers across the whole walk
-  asm volatile("" : "+s"(after), "+s"(before));
-  if (inwin)
-    (fy_step<G, Ls>(j, z, cval, disp, after, before, killm), ...);
-  else
-    (fy_step_flat<G, Ls>(j, cval, disp, after, before, killm), ...);
-  return __builtin_amdgcn_inverse_ballot_w64(killm);
 }
 
 // Dwords of a heavy record that one lane of a G-lane segment holds when the
@@ -954,11 +974,6 @@ __host__ __device__ constexpr int perm_stride(int k_max) { return ((k_max + 1 + 
 __host__ __device__ constexpr int segment_lanes(int k_max) {
   return k_max <= 256 ? 8 : (k_max <= 1024 ? 16 : 64);
 }
-// the flat resolution's ballots cover every target of the k a width serves
-static_assert(segment_lanes(256) == 8 && segment_lanes(257) == 16 &&
-                  256 < (1 << target_bits<8>()), "8-lane targets");
-static_assert(segment_lanes(1024) == 16 && segment_lanes(1025) == 64 &&
-                  1024 < (1 << target_bits<16>()), "16-lane targets");
 
 __host__ __device__ constexpr size_t light_lds_bytes() {
   return queue_bytes() + static_cast<size_t>(kMapSlots) * kWave * 4;
