@@ -63,6 +63,10 @@ def lib():
         L.gmo_release_counts.restype = None
         L.gmo_jaccard.argtypes, L.gmo_jaccard.restype = [p, p, i32], dbl
         L.gmo_wcard.argtypes, L.gmo_wcard.restype = [p, i32], dbl
+        L.gmo_merge.argtypes = [p, p, i64, i32, p, p]
+        L.gmo_merge.restype = None
+        L.gmo_setops.argtypes = [p, p, p, p, i32, p]
+        L.gmo_setops.restype = None
         L.gmo_jp_brute.argtypes = [p, p, i64, p, p, i64]
         L.gmo_jp_brute.restype = dbl
         L.gmo_set_threads.argtypes, L.gmo_set_threads.restype = [ctypes.c_int], None
@@ -173,6 +177,33 @@ def jaccard(a, b) -> float:
 def wcard(y) -> float:
     yy = np.ascontiguousarray(y, dtype=np.float64)
     return float(lib().gmo_wcard(_ptr(yy), len(yy)))
+
+
+def merge(s, y):
+    """Sketch of a union from r sketches of its parts (Sec. 2.3): arrays of
+    shape (r, k); returns (s, y) of shape (k,)."""
+    ss = np.ascontiguousarray(s, dtype=np.int32)
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    r, k = ss.shape
+    so = np.empty(k, np.int32)
+    yo = np.empty(k, np.float64)
+    lib().gmo_merge(_ptr(ss), _ptr(yy), r, k, _ptr(so), _ptr(yo))
+    return so, yo
+
+
+SETOPS = ("union", "intersection", "a_minus_b", "b_minus_a", "jaccard_w")
+
+
+def setops(sa, ya, sb, yb) -> np.ndarray:
+    """Weighted cardinalities of two sets from their sketches (k registers
+    each): [union, intersection, |A\\B|, |B\\A|, J_W] (see gmo_setops)."""
+    sa = np.ascontiguousarray(sa, dtype=np.int32)
+    sb = np.ascontiguousarray(sb, dtype=np.int32)
+    ya = np.ascontiguousarray(ya, dtype=np.float64)
+    yb = np.ascontiguousarray(yb, dtype=np.float64)
+    out = np.empty(5, np.float64)
+    lib().gmo_setops(_ptr(sa), _ptr(ya), _ptr(sb), _ptr(yb), len(sa), _ptr(out))
+    return out
 
 
 def jp_brute(ia, wa, ib, wb) -> float:

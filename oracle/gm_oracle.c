@@ -28,6 +28,12 @@
  *       (k-1)/sum_j y_j).
  *   gmo_jp_brute                      -- the probability Jaccard similarity
  *       J_P by its closed form (Sec. 1), O(n^2).
+ *   gmo_merge                         -- the sketch of a union from the
+ *       sketches of its parts (Sec. 2.3, mergeability).
+ *   gmo_setops                        -- union, intersection, relative
+ *       complements and weighted Jaccard similarity of two sets from their
+ *       sketches (the Lemiesz algebra the paper uses in Sec. 4.5; reading
+ *       stated at the function).
  *
  * Parity pins: every function above is checked by the Python suite against
  * values fixed outside this file (splitmix64 known answers, the worked
@@ -692,6 +698,107 @@ double gmo_wcard(const double *y, int32_t k)
     for (int32_t j = 0; j < k; ++j)
         sum = sum + y[j];
     return (double)(k - 1) / sum;
+}
+
+/* ------------------------------------------------------------------ */
+/* mergeability (Sec. 2.3) and the weighted-cardinality algebra of two  */
+/* sets                                                                 */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Sketch of the union of r parts from the parts' sketches (Sec. 2.3):
+ * y_j is the smallest y_j over the parts and s_j the index that came with
+ * it; equal values are ordered by index, the order every register of this
+ * oracle keeps.  Empty registers (-1, +inf) take part in nothing; a
+ * register that is poisoned (-2, NaN) in any part is poisoned.
+ * s_in/y_in: r row-major sketches of k registers.
+ */
+void gmo_merge(const int32_t *s_in, const double *y_in, int64_t r, int32_t k,
+               int32_t *s_out, double *y_out)
+{
+    for (int32_t j = 0; j < k; ++j) {
+        int32_t bs = -1;
+        double by = INFINITY;
+        int poison = 0;
+        for (int64_t q = 0; q < r; ++q) {
+            int32_t s = s_in[q * (int64_t)k + j];
+            double y = y_in[q * (int64_t)k + j];
+            if (s == -2 || isnan(y)) {
+                poison = 1;
+                continue;
+            }
+            if (s >= 0 && lexless(y, s, by, bs)) {
+                by = y;
+                bs = s;
+            }
+        }
+        s_out[j] = poison ? -2 : bs;
+        y_out[j] = poison ? NAN : by;
+    }
+}
+
+/*
+ * Weighted cardinalities of two sets A and B (each object with a fixed
+ * positive weight, Sec. 1) from their sketches.  The paper names Lemiesz's
+ * estimators of the union, intersection, relative complement and weighted
+ * Jaccard similarity (Sec. 4.5) without stating them; this is the reading
+ * used here:
+ *  - the union's sketch is the merge of the two (Sec. 2.3), so its weighted
+ *    cardinality is the Sec. 1 estimator (k-1)/sum_j y_j of the merge
+ *    (unbiased by Theorem 2);
+ *  - register j of the union is won by one object with probability
+ *    proportional to its weight (the Gumbel-Max property of Sec. 1 applied
+ *    to the union vector).  The winner lies in A and B exactly when both
+ *    sketches hold the same (y_j, s_j); in A only when A's register is the
+ *    lexicographically smaller; in B only when B's is.  The three counts over
+ *    k registers estimate |A&B|_w, |A\B|_w and |B\A|_w as fractions of the
+ *    union, and the first one is the weighted Jaccard similarity J_W (for
+ *    sets J_W equals J_P of Sec. 1);
+ *  - the winner's identity is independent of the union's register values,
+ *    so each fraction times the union estimate is unbiased for its part.
+ * out[0] = union, out[1] = intersection, out[2] = |A\B|_w, out[3] = |B\A|_w,
+ * out[4] = J_W, computed as union = (k-1) / (sum of the merged values, left
+ * to right), f = (double)count / (double)k, part = union * f.  Two empty
+ * sketches give zeros; a poisoned register makes every output NaN.
+ */
+void gmo_setops(const int32_t *sa, const double *ya, const int32_t *sb, const double *yb,
+                int32_t k, double *out)
+{
+    double sum = 0.0;
+    int64_t neq = 0, nlt = 0, ngt = 0;
+    int poison = 0;
+    for (int32_t j = 0; j < k; ++j) {
+        if (sa[j] == -2 || sb[j] == -2 || isnan(ya[j]) || isnan(yb[j])) {
+            poison = 1;
+            continue;
+        }
+        double m;
+        if (lexless(ya[j], sa[j], yb[j], sb[j])) {
+            m = ya[j];
+            if (sa[j] >= 0)
+                ++nlt;
+        } else if (lexless(yb[j], sb[j], ya[j], sa[j])) {
+            m = yb[j];
+            if (sb[j] >= 0)
+                ++ngt;
+        } else {
+            m = ya[j];
+            if (sa[j] >= 0)
+                ++neq;
+        }
+        sum = sum + m;
+    }
+    if (poison) {
+        for (int q = 0; q < 5; ++q)
+            out[q] = NAN;
+        return;
+    }
+    double uni = (double)(k - 1) / sum;
+    out[0] = uni;
+    out[1] = uni * ((double)neq / (double)k);
+    out[2] = uni * ((double)nlt / (double)k);
+    out[3] = uni * ((double)ngt / (double)k);
+    out[4] = (double)neq / (double)k;
 }
 
 /*
