@@ -115,7 +115,11 @@ gm_status gm_sketch_update(const int32_t *indices, const float *weights, const i
  * gm_sketch_plain -- plain form of Eq. (1)/(2): every (entry, register) key
  * is drawn and the minimum kept; O(k n+) per vector.  Same arguments and
  * layout as gm_sketch.  Register j of a k-register plain sketch equals
- * register j of any larger plain sketch with the same seed.
+ * register j of any larger plain sketch with the same seed.  A call with
+ * few vectors splits each vector's entries over several workgroups and
+ * merges their minima (Sec. 2.3) in a per-stream scratch area of the
+ * library (about 12 * 1536 * CUs * 256 bytes, created by the first such
+ * call or by gm_reserve).
  */
 gm_status gm_sketch_plain(const int32_t *indices, const float *weights, const int64_t *offsets,
                           int64_t nvec, int32_t k, uint64_t seed,
@@ -139,8 +143,9 @@ gm_status gm_sketch_batched(const int32_t *indices, const float *weights, const 
 /*
  * gm_reserve -- create, on the current device, the workspace that FastGM
  * calls on `stream` with up to nvec vectors need (planner lists, big-vector
- * candidate pool), so that later calls allocate nothing.  Call it before
- * capturing FastGM calls into a HIP graph on `stream`.  Synchronous.
+ * candidate pool), and the plain form's split scratch, so that later calls
+ * allocate nothing.  Call it before capturing sketch calls into a HIP graph
+ * on `stream`.  Synchronous.
  */
 gm_status gm_reserve(int64_t nvec, hipStream_t stream);
 
@@ -172,6 +177,30 @@ gm_status gm_jaccard_est_pairs(const int32_t *store_idx, int64_t nstore, int32_t
  */
 gm_status gm_wcard_est(const double *val, int64_t nvec, int32_t k, double *out,
                        hipStream_t stream);
+
+/*
+ * gm_setops -- weighted cardinalities of two sets from their sketches.  For
+ * sets whose objects carry fixed positive weights (the weighted-cardinality
+ * setting of Sec. 1), row p of (idx_a, val_a) and of (idx_b, val_b) are the
+ * sketches of A_p and B_p (same k, seed and form; row-major [npairs][k]),
+ * and out[p*5 + c] (fp64, device) receives
+ *   c = 0  |A u B|_w = (k-1) / sum_j m_j, m_j the lexicographically smaller
+ *          of the two registers (the union's sketch, Sec. 2.3; Theorem 2),
+ *          summed left to right;
+ *   c = 1  |A n B|_w = union * (#{j : registers equal and filled} / k);
+ *   c = 2  |A \ B|_w = union * (#{j : A's register smaller} / k);
+ *   c = 3  |B \ A|_w = union * (#{j : B's register smaller} / k);
+ *   c = 4  J_W(A, B) = #{j : registers equal and filled} / k.
+ * The union's register is won by one object with probability proportional
+ * to its weight (Sec. 1), in both sets exactly when the registers are equal;
+ * the paper applies these estimates (Lemiesz's algebra) in Sec. 4.5 without
+ * stating them, so this is the library's reading of them.  Each estimate is
+ * unbiased.  Two empty sketches give zeros; a poisoned register (index -2)
+ * makes all five NaN.  k >= 2; argument errors as elsewhere.
+ */
+gm_status gm_setops(const int32_t *idx_a, const double *val_a, const int32_t *idx_b,
+                    const double *val_b, int64_t npairs, int32_t k, double *out,
+                    hipStream_t stream);
 
 /*
  * gm_rate_probe -- issue-rate probe for the roofline of the sketch kernels.

@@ -19,7 +19,7 @@ from . import _native
 from ._native import GM_K_MAX, GMError  # noqa: F401
 
 __all__ = ["sketch", "sketch_batched", "reserve", "autotune", "jaccard_est", "jaccard_est_pairs", "wcard_est",
-           "merge", "get_data_errors", "reset_data_errors", "set_option", "release",
+           "merge", "setops", "get_data_errors", "reset_data_errors", "set_option", "release",
            "GMError", "GM_K_MAX", "library_path"]
 
 _FORMS = {"fastgm": _native.GM_FORM_FASTGM, "plain": _native.GM_FORM_PLAIN}
@@ -179,6 +179,28 @@ def merge(idx, val, stream=None):
                     _stream(stream))
     _native.check(st, "gm_merge")
     return oi, ov
+
+
+SETOPS = ("union", "intersection", "a_minus_b", "b_minus_a", "jaccard_w")
+
+
+def setops(idx_a, val_a, idx_b, val_b, out=None, stream=None):
+    """Weighted cardinalities of set pairs from their [npairs, k] sketches
+    (gm_setops): returns fp64 [npairs, 5] = union, intersection, A minus B,
+    B minus A, weighted Jaccard (columns named in SETOPS)."""
+    torch = _torch()
+    L = _native.load()
+    npairs, k = idx_a.shape
+    for t in (val_a, idx_b, val_b):
+        if tuple(t.shape) != (npairs, k):
+            raise ValueError("sketch shapes differ")
+    if out is None:
+        out = torch.empty((npairs, 5), dtype=torch.float64, device=idx_a.device)
+    st = L.gm_setops(_dev(idx_a, torch.int32, "idx_a"), _dev(val_a, torch.float64, "val_a"),
+                     _dev(idx_b, torch.int32, "idx_b"), _dev(val_b, torch.float64, "val_b"),
+                     npairs, k, _dev(out, torch.float64, "out"), _stream(stream))
+    _native.check(st, "gm_setops")
+    return out
 
 
 class LshIndex:

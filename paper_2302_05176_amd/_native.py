@@ -65,6 +65,7 @@ def load() -> ctypes.CDLL:
     L.gm_jaccard_est_pairs.argtypes = [p, i64, i32, p, p, i64, p, p]
     L.gm_wcard_est.argtypes = [p, i64, i32, p, p]
     L.gm_merge.argtypes = [p, p, i64, i32, p, p, p]
+    L.gm_setops.argtypes = [p, p, p, p, i64, i32, p, p]
     L.gm_rate_probe.argtypes = [i32, i64, i32, u64, p, p]
     L.gm_lsh_build.argtypes = [p, i64, i32, i32, i32, ctypes.POINTER(p), p]
     L.gm_lsh_query.argtypes = [p, p, i64, i32, p, p, p]
@@ -92,7 +93,7 @@ def load() -> ctypes.CDLL:
     L.gm_release.argtypes = []
     L.gm_release.restype = None
     for name in ("gm_sketch", "gm_sketch_plain", "gm_sketch_batched", "gm_jaccard_est",
-                 "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_get_data_errors",
+                 "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_setops", "gm_get_data_errors",
                  "gm_reset_data_errors", "gm_set_option", "gm_get_stats", "gm_reset_stats", "gm_reserve", "gm_autotune",
                  "gm_serve_run", "gm_lsh_build", "gm_lsh_query", "gm_lsh_info"):
         getattr(L, name).restype = st

@@ -51,18 +51,47 @@ def up_to_date() -> bool:
     return all(os.path.getmtime(d) <= t for d in deps)
 
 
+OBJDIR = os.path.join(ROOT, "_build")
+
+
+def _compile(src: str, obj: str, verbose: bool):
+    flags = [f for f in FLAGS if f != "-shared"]
+    cmd = ([hipcc(), f"--offload-arch={ARCH}"] + flags +
+           ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    return subprocess.run(cmd, capture_output=True, text=True)
+
+
 def build(force: bool = True, verbose: bool = False) -> str:
-    """Compile every HIP source into libgm.so (always when force=True)."""
+    """Compile every HIP source into libgm.so (always when force=True): one
+    hipcc per source in parallel, then one link."""
     if not force and up_to_date():
         return LIB
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(OBJDIR, exist_ok=True)
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(OBJDIR, os.path.splitext(s)[0] + "." + tag + ".o") for s in SOURCES]
+    jobs = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(SOURCES, objs)))
+    for src, res in zip(SOURCES, results):
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"hipcc failed on {src}")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = command(tmp)
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
+    for o in objs:
+        try:
+            os.remove(o)
+        except OSError:
+            pass
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libgm.so")
+        raise RuntimeError("hipcc failed linking libgm.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -11,7 +11,9 @@
 #include "gm_common.h"
 
 namespace gm {
-hipError_t launch_plain(const SketchArgs& p, hipStream_t stream);
+hipError_t launch_plain(const SketchArgs& p, void* scratch, int cus, hipStream_t stream);
+int64_t plain_scratch_regs(int cus);
+int64_t plain_scratch_counters(int cus);
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
                          int republish, double seg_rest, int small_waves, int32_t* list,
                          void* plan, void* big, int32_t* pool, int64_t pool_cap,
@@ -34,6 +36,8 @@ hipError_t launch_wcard(const double* val, int64_t nvec, int32_t k, double* out,
 hipError_t launch_merge(const int32_t* in_idx, const double* in_val, int64_t r, int32_t k,
                         int32_t* out_idx, double* out_val, hipStream_t stream);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream);
+hipError_t launch_setops(const int32_t* sa, const double* ya, const int32_t* sb, const double* yb,
+                         int64_t npairs, int32_t k, double* out, hipStream_t stream);
 hipError_t launch_rate_probe(int what, int64_t lanes, int32_t steps, uint64_t seed_mix,
                              double* out, hipStream_t stream);
 }  // namespace gm
@@ -57,6 +61,7 @@ struct PlanWorkspace {
   void* heavy = nullptr;      // per-wave heavy-element lists of the FastGM walk
   int64_t heavy_waves = 0;
   void* part = nullptr;       // partial sketches of split big-vector walks
+  void* plain = nullptr;      // partial registers and counters of split plain launches
 };
 
 // Resident waves per CU the heavy lists are sized for: the FastGM kernels
@@ -175,6 +180,32 @@ gm_status plan_workspace(DeviceState* st, hipStream_t stream, int64_t nvec, Plan
   return GM_OK;
 }
 
+size_t plain_scratch_bytes(int cus) {
+  return static_cast<size_t>(gm::plain_scratch_regs(cus)) * (sizeof(double) + sizeof(int32_t)) +
+         2 * sizeof(int32_t) * static_cast<size_t>(gm::plain_scratch_counters(cus));
+}
+
+// Scratch of split plain launches on `stream` (created on first use, with
+// its counters zeroed; the kernel leaves them at zero).
+gm_status plain_workspace(DeviceState* st, hipStream_t stream, void** out) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  PlanWorkspace& ws = st->plans[stream];
+  if (!ws.plain) {
+    void* q = nullptr;
+    const size_t bytes = plain_scratch_bytes(st->cus);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return from_hip(e);
+    e = hipMemset(q, 0, bytes);
+    if (e != hipSuccess) {
+      (void)hipFree(q);
+      return from_hip(e);
+    }
+    ws.plain = q;
+  }
+  *out = ws.plain;
+  return GM_OK;
+}
+
 gm_status sketch_common(const int32_t* indices, const float* weights, const int64_t* offsets,
                         int64_t nvec, int32_t k_uniform, const int32_t* kvec,
                         const int64_t* outoff, int32_t k_max, uint64_t seed, gm_form form,
@@ -200,7 +231,12 @@ gm_status sketch_common(const int32_t* indices, const float* weights, const int6
   a.out_idx = out_idx;
   a.out_val = out_val;
   a.err = st->err;
-  if (form == GM_FORM_PLAIN) return from_hip(gm::launch_plain(a, stream));
+  if (form == GM_FORM_PLAIN) {
+    void* scratch = nullptr;
+    s = plain_workspace(st, stream, &scratch);
+    if (s != GM_OK) return s;
+    return from_hip(gm::launch_plain(a, scratch, st->cus, stream));
+  }
   if (nvec > 0x7FFFFFFF) return GM_ERR_UNSUPPORTED;
   PlanWorkspace* ws = nullptr;
   s = plan_workspace(st, stream, nvec, &ws);
@@ -254,7 +290,10 @@ gm_status gm_reserve(int64_t nvec, hipStream_t stream) {
   gm_status s = device_state(&st);
   if (s != GM_OK) return s;
   PlanWorkspace* ws = nullptr;
-  return plan_workspace(st, stream, nvec > 0 ? nvec : 1, &ws);
+  s = plan_workspace(st, stream, nvec > 0 ? nvec : 1, &ws);
+  if (s != GM_OK) return s;
+  void* scratch = nullptr;
+  return plain_workspace(st, stream, &scratch);
 }
 
 gm_status gm_jaccard_est(const int32_t* idx_a, const int32_t* idx_b, int64_t npairs, int32_t k,
@@ -300,6 +339,15 @@ gm_status gm_merge(const int32_t* in_idx, const double* in_val, int64_t r, int32
   if (r < 1 || k < 1) return GM_ERR_INVALID_ARG;
   if (!in_idx || !in_val || !out_idx || !out_val) return GM_ERR_INVALID_ARG;
   return from_hip(gm::launch_merge(in_idx, in_val, r, k, out_idx, out_val, stream));
+}
+
+gm_status gm_setops(const int32_t* idx_a, const double* val_a, const int32_t* idx_b,
+                    const double* val_b, int64_t npairs, int32_t k, double* out,
+                    hipStream_t stream) {
+  if (npairs < 0 || k < 2) return GM_ERR_INVALID_ARG;
+  if (npairs == 0) return GM_OK;
+  if (!idx_a || !val_a || !idx_b || !val_b || !out) return GM_ERR_INVALID_ARG;
+  return from_hip(gm::launch_setops(idx_a, val_a, idx_b, val_b, npairs, k, out, stream));
 }
 
 gm_status gm_get_data_errors(int64_t* host_count, hipStream_t stream) {
@@ -427,6 +475,7 @@ void gm_release_stream(hipStream_t stream) {
   if (it->second.pool) (void)hipFree(it->second.pool);
   if (it->second.heavy) (void)hipFree(it->second.heavy);
   if (it->second.part) (void)hipFree(it->second.part);
+  if (it->second.plain) (void)hipFree(it->second.plain);
   st.plans.erase(it);
 }
 
@@ -449,6 +498,7 @@ void gm_release(void) {
       if (kv.second.pool) (void)hipFree(kv.second.pool);
       if (kv.second.heavy) (void)hipFree(kv.second.heavy);
       if (kv.second.part) (void)hipFree(kv.second.part);
+      if (kv.second.plain) (void)hipFree(kv.second.plain);
     }
     st.plans.clear();
   }

@@ -7,6 +7,8 @@
 //    sum taken left to right.  One thread per sketch.
 //  * Merge (Sec. 2.3): registerwise lexicographic (y, s) minimum over r
 //    sketches.  One thread per register.
+//  * Two-set algebra: union, intersection, relative complements and J_W of
+//    two sets from their sketches (see setops_kernel).
 #include "gm_common.h"
 
 namespace gm {
@@ -95,6 +97,88 @@ __global__ __launch_bounds__(256) void merge_kernel(const int32_t* in_idx, const
   out_val[j] = poison ? bitsd(kNanBits) : by;
 }
 
+// Weighted cardinalities of two sets A and B from their sketches (union,
+// intersection, A minus B, B minus A, J_W).  Register j of the union is the
+// lexicographic minimum of the two registers (Sec. 2.3); its winner lies in
+// both sets when the two registers are equal, in A only when A's is the
+// smaller, in B only when B's is.  The union's weighted cardinality is the
+// Sec. 1 estimator (k-1)/sum_j y_j of the merged values, summed left to
+// right; each part is the union times its fraction of the k registers.
+//
+// One thread per pair, so that its sum keeps the left-to-right order.  The
+// rows are read through LDS in tiles of kSetTile registers: the wave loads
+// 64 pairs x kSetTile registers with consecutive lanes on consecutive
+// addresses, then each lane runs through its own pair's tile.
+constexpr int kSetPairs = 64;   // pairs per workgroup (one wave)
+constexpr int kSetTile = 16;    // registers per tile
+
+__global__ __launch_bounds__(kSetPairs) void setops_kernel(const int32_t* sa, const double* ya,
+                                                           const int32_t* sb, const double* yb,
+                                                           int64_t npairs, int32_t k, double* out) {
+  __shared__ double t_ya[kSetPairs][kSetTile + 1];
+  __shared__ double t_yb[kSetPairs][kSetTile + 1];
+  __shared__ int32_t t_sa[kSetPairs][kSetTile + 1];
+  __shared__ int32_t t_sb[kSetPairs][kSetTile + 1];
+  const int lane = threadIdx.x;
+  for (int64_t p0 = static_cast<int64_t>(blockIdx.x) * kSetPairs; p0 < npairs;
+       p0 += static_cast<int64_t>(gridDim.x) * kSetPairs) {
+    const int np = npairs - p0 < kSetPairs ? static_cast<int>(npairs - p0) : kSetPairs;
+    double sum = 0.0;
+    int64_t neq = 0, nlt = 0, ngt = 0;
+    bool poison = false;
+    for (int j0 = 0; j0 < k; j0 += kSetTile) {
+      const int nj = k - j0 < kSetTile ? k - j0 : kSetTile;
+      // stage: element e of the (np x nj) tile goes to lane e % 64
+      for (int e = lane; e < np * nj; e += kSetPairs) {
+        const int q = e / nj, jj = e - q * nj;
+        const int64_t g = (p0 + q) * static_cast<int64_t>(k) + j0 + jj;
+        t_ya[q][jj] = ya[g];
+        t_yb[q][jj] = yb[g];
+        t_sa[q][jj] = sa[g];
+        t_sb[q][jj] = sb[g];
+      }
+      __syncthreads();
+      if (lane < np) {
+        for (int jj = 0; jj < nj; ++jj) {
+          const double a = t_ya[lane][jj], b = t_yb[lane][jj];
+          const int32_t ia = t_sa[lane][jj], ib = t_sb[lane][jj];
+          if (ia == kIdxPoison || ib == kIdxPoison || a != a || b != b) {
+            poison = true;
+            continue;
+          }
+          double m;
+          if (a < b || (a == b && ia < ib)) {
+            m = a;
+            nlt += ia >= 0 ? 1 : 0;
+          } else if (b < a || (a == b && ib < ia)) {
+            m = b;
+            ngt += ib >= 0 ? 1 : 0;
+          } else {
+            m = a;
+            neq += ia >= 0 ? 1 : 0;
+          }
+          sum = sum + m;
+        }
+      }
+      __syncthreads();
+    }
+    if (lane < np) {
+      double* o = out + (p0 + lane) * 5;
+      if (poison) {
+        for (int c = 0; c < 5; ++c) o[c] = bitsd(kNanBits);
+      } else {
+        const double uni = static_cast<double>(k - 1) / sum;
+        const double dk = static_cast<double>(k);
+        o[0] = uni;
+        o[1] = uni * (static_cast<double>(neq) / dk);
+        o[2] = uni * (static_cast<double>(nlt) / dk);
+        o[3] = uni * (static_cast<double>(ngt) / dk);
+        o[4] = static_cast<double>(neq) / dk;
+      }
+    }
+  }
+}
+
 __global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
 
 static unsigned grid_for(int64_t items, int per_block) {
@@ -130,6 +214,13 @@ hipError_t launch_merge(const int32_t* in_idx, const double* in_val, int64_t r, 
                         int32_t* out_idx, double* out_val, hipStream_t stream) {
   hipLaunchKernelGGL(merge_kernel, dim3(grid_for(k, 256)), dim3(256), 0, stream, in_idx, in_val, r,
                      k, out_idx, out_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_setops(const int32_t* sa, const double* ya, const int32_t* sb, const double* yb,
+                         int64_t npairs, int32_t k, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(setops_kernel, dim3(grid_for(npairs, kSetPairs)), dim3(kSetPairs), 0, stream,
+                     sa, ya, sb, yb, npairs, k, out);
   return hipGetLastError();
 }
 

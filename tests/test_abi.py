@@ -28,7 +28,7 @@ def test_header_declares_expected_entry_points():
     syms = declared_symbols()
     for s in ("gm_sketch", "gm_sketch_plain", "gm_sketch_batched", "gm_sketch_update",
               "gm_jaccard_est",
-              "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_get_data_errors",
+              "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_setops", "gm_get_data_errors",
               "gm_lsh_build", "gm_lsh_query", "gm_lsh_free", "gm_release"):
         assert s in syms
 
@@ -57,6 +57,10 @@ def test_host_side_argument_validation(lib):
     assert lib.gm_sketch_batched(fake, fake, fake, 1, fake, fake, 8, u, 7, fake, fake,
                                  nul) == N.GM_ERR_INVALID_ARG
     assert lib.gm_wcard_est(fake, 1, 1, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_setops(fake, fake, fake, fake, 1, 1, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_setops(fake, fake, fake, fake, -1, 8, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_setops(fake, nul, fake, fake, 1, 8, fake, nul) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_setops(nul, nul, nul, nul, 0, 8, nul, nul) == N.GM_OK
     assert lib.gm_jaccard_est(fake, fake, -1, 8, fake, nul) == N.GM_ERR_INVALID_ARG
     assert lib.gm_jaccard_est_pairs(fake, 1, 8, nul, fake, 1, fake, nul) == N.GM_ERR_INVALID_ARG
     assert lib.gm_merge(fake, fake, 0, 8, fake, fake, nul) == N.GM_ERR_INVALID_ARG

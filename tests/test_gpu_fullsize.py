@@ -11,7 +11,9 @@ computed by the oracle on its own, plus properties that hold at any size.
   4 sqrt(1/((k-2) 100)) (Theorem 2), and two seeds' estimates equal the
   oracle's.
 * uneven batch: 10^5 vectors (4.7x10^8 entries), per-vector k, autotuned and
-  replayed from a captured graph; sampled vectors.
+  replayed from a captured graph; every register.  The plain form through
+  the batched call on a seeded 1% sample, every register.
+* stream vector, plain form at k = 1024: every register.
 * serving: a store of 10^6 sketches at k = 512 and 20,000 requests; sampled
   stored rows, sketch requests and Jaccard answers.
 
@@ -120,8 +122,24 @@ def test_stream_vector_full(gm, k):
     assert abs(r.mean() - 1.0) < 4.0 * np.sqrt(1.0 / ((k - 2) * 100))
 
 
-@pytest.mark.timeout(600)
-def test_uneven_batch_full_sampled(gm, tmp_path, monkeypatch):
+def _rows_of(off, vs):
+    """Entry positions of vectors vs, concatenated, and their CSR offsets."""
+    lens = (off[vs + 1] - off[vs]).astype(np.int64)
+    sub = np.zeros(len(vs) + 1, np.int64)
+    np.cumsum(lens, out=sub[1:])
+    pos = np.repeat(off[vs] - sub[:-1], lens) + np.arange(sub[-1], dtype=np.int64)
+    return pos, sub
+
+
+def _regs_of(outoff, vs, kv):
+    """Flat register positions of vectors vs (each with kv registers)."""
+    return (outoff[vs][:, None] + np.arange(kv, dtype=np.int64)[None, :])
+
+
+@pytest.mark.timeout(900)
+def test_uneven_batch_full(gm, tmp_path, monkeypatch):
+    """Every register of the 10^5-vector uneven batch (autotuned, replayed
+    from a captured graph) against the oracle, one oracle call per k."""
     monkeypatch.setenv("GM_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
     nvec, seed = 100_000, 1
     print("uneven batch: generating 10^5 vectors", flush=True)
@@ -150,24 +168,59 @@ def test_uneven_batch_full_sampled(gm, tmp_path, monkeypatch):
         torch.cuda.synchronize()
     finally:
         gm.reset_options()
-    nplus = np.diff(off)
-    rng = np.random.default_rng(78)
-    sample = set(np.argsort(nplus)[-8:].tolist())           # the largest vectors
+    gs_all, gy_all = oi.cpu().numpy(), ov.cpu().numpy()
+    del oi, ov
     for kv in (64, 256, 1024, 4096):
-        sample |= set(rng.choice(np.nonzero(kk == kv)[0], 25, replace=False).tolist())
-    sample = np.array(sorted(sample))
-    # gather the sampled rows on the device, then copy them back
-    rows = np.concatenate([np.arange(outoff[v], outoff[v + 1]) for v in sample])
-    tr = _dev(rows)
-    gs, gy = oi[tr].cpu().numpy(), ov[tr].cpu().numpy()
-    print(f"uneven batch: {len(sample)} sampled vectors against the oracle", flush=True)
-    pos = 0
-    for v in sample:
-        a, b, kv = off[v], off[v + 1], int(kk[v])
-        ws, wy = oracle.sketch(idx[a:b], w[a:b], np.array([0, b - a]), kv, seed,
-                               form=oracle.FORM_STREAM)
-        _same(gs[pos:pos + kv], gy[pos:pos + kv], ws[0], wy[0], f"vector {v} (n+={b - a}, k={kv})")
-        pos += kv
+        vs = np.nonzero(kk == kv)[0]
+        pos, sub = _rows_of(off, vs)
+        print(f"uneven batch: oracle on the {len(vs)} vectors with k={kv}", flush=True)
+        ws, wy = oracle.sketch(idx[pos], w[pos], sub, kv, seed, form=oracle.FORM_STREAM)
+        r = _regs_of(outoff, vs, kv)
+        _same(gs_all[r], gy_all[r], ws, wy, f"k={kv}")
+
+
+@pytest.mark.timeout(600)
+def test_uneven_batch_plain_sample(gm):
+    """The plain form through gm_sketch_batched on a seeded 1% sample of the
+    uneven batch (1000 vectors, all four k), every register."""
+    nvec, seed = 100_000, 1
+    idx, w, off, kk = W.uneven(nvec=nvec)
+    rng = np.random.default_rng(80)
+    vs = np.sort(rng.choice(nvec, nvec // 100, replace=False))
+    pos, sub = _rows_of(off, vs)
+    si, sw, sk = idx[pos], w[pos], kk[vs]
+    outoff = np.zeros(len(vs) + 1, np.int64)
+    np.cumsum(sk, out=outoff[1:])
+    print(f"uneven batch plain: {len(vs)} sampled vectors, {int(sub[-1])} entries", flush=True)
+    gs, gy = gm.sketch_batched(_dev(si), _dev(sw), _dev(sub), _dev(sk), _dev(outoff), 4096, seed,
+                               form="plain")
+    torch.cuda.synchronize()
+    gs, gy = gs.cpu().numpy(), gy.cpu().numpy()
+    for kv in (64, 256, 1024, 4096):
+        loc = np.nonzero(sk == kv)[0]
+        p2, s2 = _rows_of(sub, loc)
+        print(f"uneven batch plain: oracle on {len(loc)} vectors k={kv}", flush=True)
+        ws, wy = oracle.sketch(si[p2], sw[p2], s2, kv, seed, form=oracle.FORM_PLAIN)
+        r = _regs_of(outoff, loc, kv)
+        _same(gs[r], gy[r], ws, wy, f"plain k={kv}")
+
+
+@pytest.mark.timeout(600)
+def test_stream_vector_plain_full(gm):
+    """The plain form of the 10^7-entry stream vector at k = 1024, launched as
+    bench.py times it (entries split over the GPU, minima merged), every
+    register; the oracle sketches 64 ranges in parallel and merges them
+    (Sec. 2.3, pinned to the sketch of the union)."""
+    idx, w, off = W.stream(nplus=10_000_000)
+    k, seed = 1024, 1
+    print("stream vector n+=10^7 k=1024 plain form", flush=True)
+    s, y = gm.sketch(_dev(idx), _dev(w), _dev(off), k, seed, form="plain")
+    torch.cuda.synchronize()
+    print("stream vector plain: oracle, 64 ranges on 16 threads", flush=True)
+    cut = np.linspace(0, len(idx), 65).astype(np.int64)
+    ps, py = oracle.sketch(idx, w, cut, k, seed, form=oracle.FORM_PLAIN)
+    ws, wy = oracle.merge(ps, py)
+    _same(s.cpu().numpy()[0], y.cpu().numpy()[0], ws, wy, "plain k=1024")
 
 
 def test_serving_full_sampled(gm):

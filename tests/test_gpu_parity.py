@@ -402,3 +402,158 @@ def test_autotune_keeps_results_and_caches(gm, tmp_path, monkeypatch):
                      oracle.sketch(idx, w, off, 128, 3, form=oracle.FORM_STREAM), "tuned")
     finally:
         gm.reset_options()
+
+
+def _edge_rows(k, seed):
+    """Oracle-made sketch rows covering the estimators' special cases:
+    0 A, 1 B (shares most of A's support, same weights), 2 empty, 3 zero
+    weights only (empty too), 4 poisoned, 5 one element, 6 a set disjoint
+    from A."""
+    rng = np.random.default_rng(seed)
+    a_i = W.distinct_sorted(rng, 300, 1 << 20)
+    a_w = W.exp1_weights(rng, 300)
+    b_i = np.concatenate([a_i[:200], W.distinct_sorted(rng, 50, 1 << 20) + (1 << 21)])
+    b_w = np.concatenate([a_w[:200], W.exp1_weights(rng, 50)])
+    rows_i = [a_i, b_i, np.zeros(0), np.array([3, 4]), np.array([5, 6]), np.array([77]),
+              W.distinct_sorted(rng, 120, 1 << 20) + (1 << 22)]
+    rows_w = [a_w, b_w, np.zeros(0), np.zeros(2), np.array([1.0, -1.0]), np.array([0.5]),
+              W.exp1_weights(rng, 120)]
+    idx, w, off = W._pack(rows_i, rows_w)
+    return oracle.sketch(idx, w, off, k, seed, form=oracle.FORM_STREAM)
+
+
+def _nan_same(got, want, what):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    assert np.array_equal(np.isnan(got), np.isnan(want)), what
+    fin = ~np.isnan(want)
+    assert np.array_equal(got[fin].view(np.uint64), want[fin].view(np.uint64)), what
+
+
+@pytest.mark.parametrize("k", [64, 1000])
+def test_estimators_on_empty_and_poisoned_sketches(gm, k):
+    """gm_jaccard_est, gm_jaccard_est_pairs, gm_wcard_est, gm_merge and
+    gm_setops on oracle-made rows that are empty, zero-weight, poisoned or a
+    single element, against the oracle's estimators on the same rows."""
+    s, y = _edge_rows(k, 40 + k)
+    assert np.all(s[2] == -1) and np.all(s[3] == -1) and np.all(s[4] == -2)
+    pairs = [(0, 1), (0, 2), (2, 2), (2, 3), (4, 0), (4, 4), (5, 5), (0, 0), (0, 6), (6, 2), (1, 0)]
+    ia = np.array([p[0] for p in pairs], np.int64)
+    ib = np.array([p[1] for p in pairs], np.int64)
+    ts, ty = torch.from_numpy(s).to(DEV), torch.from_numpy(y).to(DEV)
+    # Jaccard, row pairs and store lookups
+    J = gm.jaccard_est(ts[torch.from_numpy(ia).to(DEV)].contiguous(),
+                       ts[torch.from_numpy(ib).to(DEV)].contiguous()).cpu().numpy()
+    Jp = gm.jaccard_est_pairs(ts, torch.from_numpy(ia).to(DEV),
+                              torch.from_numpy(ib).to(DEV)).cpu().numpy()
+    Jo = np.array([oracle.jaccard(s[a], s[b]) for a, b in pairs])
+    _nan_same(J, Jo, "jaccard_est")
+    _nan_same(Jp, Jo, "jaccard_est_pairs")
+    assert Jo[2] == 0.0 and Jo[5] == 0.0 and Jo[7] == 1.0
+    # weighted cardinality of every row
+    C = gm.wcard_est(ty).cpu().numpy()
+    _nan_same(C, np.array([oracle.wcard(y[r]) for r in range(len(y))]), "wcard_est")
+    assert C[2] == 0.0 and np.isnan(C[4])
+    # merges of groups of rows
+    for grp in ([0, 2], [2, 3], [4, 0], [0, 1, 2], [5], [1, 6, 3]):
+        g = torch.from_numpy(np.array(grp, np.int64)).to(DEV)
+        mi, mv = gm.merge(ts[g].contiguous(), ty[g].contiguous())
+        torch.cuda.synchronize()
+        os_, oy = oracle.merge(s[grp], y[grp])
+        assert np.array_equal(mi.cpu().numpy(), os_), f"merge {grp}"
+        _nan_same(mv.cpu().numpy(), oy, f"merge {grp}")
+    # two-set algebra of each pair
+    g_a, g_b = torch.from_numpy(ia).to(DEV), torch.from_numpy(ib).to(DEV)
+    R = gm.setops(ts[g_a].contiguous(), ty[g_a].contiguous(), ts[g_b].contiguous(),
+                  ty[g_b].contiguous()).cpu().numpy()
+    for p, (a, b) in enumerate(pairs):
+        _nan_same(R[p], oracle.setops(s[a], y[a], s[b], y[b]), f"setops {a},{b}")
+
+
+@pytest.mark.parametrize("k", [2, 256, 1000, 4096])
+def test_setops_match_oracle(gm, k):
+    """gm_setops on 150 oracle-made set pairs (a ragged number of 64-pair
+    groups; k both a multiple of the 16-register tile and not)."""
+    npairs = 150
+    idx, w, off, _ = W.pairs(npairs=npairs, seed=900 + k, equal_shared_weights=True)
+    oracle.set_threads(8)
+    s, y = oracle.sketch(idx, w, off, k, 6, form=oracle.FORM_STREAM)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    R = gm.setops(t(s[0::2]), t(y[0::2]), t(s[1::2]), t(y[1::2])).cpu().numpy()
+    want = np.stack([oracle.setops(s[2 * p], y[2 * p], s[2 * p + 1], y[2 * p + 1])
+                     for p in range(npairs)])
+    assert np.array_equal(R.view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.parametrize("k", [1000, 4096])
+def test_plain_large_k(gm, k):
+    """Plain form at up to 16 register tiles: a mixed batch (every vector's
+    registers against the oracle)."""
+    idx, w, off = W.mixed(seed=310 + k, nvec=24, max_n=900)
+    oracle.set_threads(8)
+    print(f"plain mixed batch k={k}", flush=True)
+    _assert_same(_gpu_sketch(gm, idx, w, off, k, 5, "plain"),
+                 oracle.sketch(idx, w, off, k, 5, form=oracle.FORM_PLAIN), f"plain k={k}")
+
+
+def _oracle_plain_split(idx, w, k, seed, parts=64):
+    """The oracle's plain sketch of one long vector: its entries in `parts`
+    ranges, sketched in parallel and merged (Sec. 2.3; the merge is pinned to
+    the sketch of the union)."""
+    n = len(idx)
+    cut = np.linspace(0, n, parts + 1).astype(np.int64)
+    s, y = oracle.sketch(idx, w, cut, k, seed, form=oracle.FORM_PLAIN)
+    return oracle.merge(s, y)
+
+
+@pytest.mark.parametrize("k", [256, 1024])
+def test_plain_split_few_vectors(gm, k):
+    """A call with few vectors splits their entries over many workgroups and
+    merges the partial minima: one 200,000-entry vector, then a small batch
+    of sizes around the split's 1024-entry minimum (every register against
+    the oracle); two calls in a row reuse the merge counters."""
+    oracle.set_threads(16)
+    idx, w, off = W.stream(nplus=200_000, seed=1017)
+    want = _oracle_plain_split(idx, w, k, 4)
+    for rep in range(2):
+        print(f"plain split: one 2e5-entry vector k={k} call {rep}", flush=True)
+        gs, gy = _gpu_sketch(gm, idx, w, off, k, 4, "plain")
+        _assert_same((gs[0], gy[0]), want, f"k={k} call {rep}")
+    sizes = np.array([1, 1023, 1024, 1025, 5000, 30_000, 0, 70_000])
+    bi, bw, bo = W.batch(nvec=len(sizes), seed=1018, sizes=sizes)
+    print(f"plain split: 8 vectors k={k}", flush=True)
+    _assert_same(_gpu_sketch(gm, bi, bw, bo, k, 4, "plain"),
+                 oracle.sketch(bi, bw, bo, k, 4, form=oracle.FORM_PLAIN), f"batch k={k}")
+
+
+def test_plain_split_poison_and_batched(gm):
+    """Split launches: an invalid entry in one range of a long vector poisons
+    the whole vector (once in the error counter), and per-vector k in a
+    batched call (k from 3 to 4096, so tiles past a vector's k are skipped)."""
+    idx, w, off = W.stream(nplus=120_000, seed=1019)
+    w = w.copy()
+    w[77_777] = -1.0
+    gm.reset_data_errors()
+    gs, gy = _gpu_sketch(gm, idx, w, off, 512, 8, "plain")
+    assert np.all(gs == -2) and np.all(np.isnan(gy))
+    assert gm.get_data_errors() == 1
+    gm.reset_data_errors()
+    # the same counters again, clean input
+    w[77_777] = 0.5
+    oracle.set_threads(16)
+    gs, gy = _gpu_sketch(gm, idx, w, off, 512, 8, "plain")
+    _assert_same((gs[0], gy[0]), _oracle_plain_split(idx, w, 512, 8), "after poison")
+    sizes = np.array([40_000, 3, 9_000, 2_500])
+    kk = np.array([4096, 3, 1000, 64], np.int32)
+    bi, bw, bo = W.batch(nvec=4, seed=1021, sizes=sizes)
+    outoff = np.zeros(5, np.int64)
+    np.cumsum(kk, out=outoff[1:])
+    t = lambda a: torch.from_numpy(a).to(DEV)
+    s, y = gm.sketch_batched(t(bi), t(bw), t(bo), t(kk), t(outoff), 4096, 12, form="plain")
+    torch.cuda.synchronize()
+    s, y = s.cpu().numpy(), y.cpu().numpy()
+    for v in range(4):
+        a, b = bo[v], bo[v + 1]
+        ws, wy = _oracle_plain_split(bi[a:b], bw[a:b], int(kk[v]), 12, parts=16)
+        _assert_same((s[outoff[v]:outoff[v + 1]], y[outoff[v]:outoff[v + 1]]), (ws, wy),
+                     f"batched v={v}")
