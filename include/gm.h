@@ -48,10 +48,12 @@
  *     offsets[v+1] < offsets[v]) are detected on the device: the vector's
  *     registers become (index -2, value NaN) and a sticky per-device counter
  *     is incremented once per bad vector (read it with gm_get_data_errors).
- *   - The library keeps a small workspace per device and per stream (an error
- *     counter, and for the FastGM form a planner list of nvec int32), created
- *     or grown by the first call that needs it -- make that call outside any
- *     stream capture -- and released by gm_release().
+ *   - The library keeps a workspace per device and per stream (for the
+ *     FastGM form a planner list of nvec int32 and the walk's lists, for the
+ *     plain form a split scratch), created or grown by the first call that
+ *     needs it -- make that call outside any stream capture -- and released
+ *     by gm_release().  The per-device error counter is static device memory
+ *     and survives gm_release().
  */
 #ifndef GM_H
 #define GM_H
@@ -124,6 +126,27 @@ gm_status gm_sketch_update(const int32_t *indices, const float *weights, const i
 gm_status gm_sketch_plain(const int32_t *indices, const float *weights, const int64_t *offsets,
                           int64_t nvec, int32_t k, uint64_t seed,
                           int32_t *out_idx, double *out_val, hipStream_t stream);
+
+/*
+ * gm_sketch_plain_noalloc -- gm_sketch_plain for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, layout, results and
+ * error rules as gm_sketch_plain; it calls no hipMalloc, hipFree or other
+ * allocating routine, not even on its first call on a device.
+ *   Scratch: the partial registers of a split launch live in one static
+ *   device array per device of 6 MiB + 32 KiB (2^19 partial registers and
+ *   2 x 4096 int32 counters), held until the process ends.  A call splits
+ *   its vectors only as far as that array holds (one vector at any k fits
+ *   the full split); a call that would need more runs with fewer entry
+ *   ranges, so no input is rejected for its size.  The counters are cleared
+ *   by a fill kernel on `stream` at the start of each split call.
+ *   Concurrency: every call on a device shares that device's array, so
+ *   calls on one device that overlap in time (different streams, or host
+ *   threads) race and may return wrong registers; serialise them.
+ */
+gm_status gm_sketch_plain_noalloc(const int32_t *indices, const float *weights,
+                                  const int64_t *offsets, int64_t nvec, int32_t k, uint64_t seed,
+                                  int32_t *out_idx, double *out_val, hipStream_t stream);
 
 /*
  * gm_sketch_batched -- vectors with individual register counts, in one call.

@@ -59,6 +59,7 @@ def load() -> ctypes.CDLL:
     st = ctypes.c_int
     L.gm_sketch.argtypes = [p, p, p, i64, i32, u64, p, p, p]
     L.gm_sketch_plain.argtypes = [p, p, p, i64, i32, u64, p, p, p]
+    L.gm_sketch_plain_noalloc.argtypes = [p, p, p, i64, i32, u64, p, p, p]
     L.gm_sketch_update.argtypes = [p, p, p, i64, i32, u64, p, p, p]
     L.gm_sketch_batched.argtypes = [p, p, p, i64, p, p, i32, u64, ctypes.c_int, p, p, p]
     L.gm_jaccard_est.argtypes = [p, p, i64, i32, p, p]
@@ -92,7 +93,7 @@ def load() -> ctypes.CDLL:
     L.gm_release_stream.restype = None
     L.gm_release.argtypes = []
     L.gm_release.restype = None
-    for name in ("gm_sketch", "gm_sketch_plain", "gm_sketch_batched", "gm_jaccard_est",
+    for name in ("gm_sketch", "gm_sketch_plain", "gm_sketch_plain_noalloc", "gm_sketch_batched", "gm_jaccard_est",
                  "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_setops", "gm_get_data_errors",
                  "gm_reset_data_errors", "gm_set_option", "gm_get_stats", "gm_reset_stats", "gm_reserve", "gm_autotune",
                  "gm_serve_run", "gm_lsh_build", "gm_lsh_query", "gm_lsh_info"):

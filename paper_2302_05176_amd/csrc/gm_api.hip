@@ -11,7 +11,7 @@
 #include "gm_common.h"
 
 namespace gm {
-hipError_t launch_plain(const SketchArgs& p, void* scratch, int cus, hipStream_t stream);
+hipError_t launch_plain(const SketchArgs& p, const PlainScratch& ps, int cus, hipStream_t stream);
 int64_t plain_scratch_regs(int cus);
 int64_t plain_scratch_counters(int cus);
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
@@ -71,9 +71,30 @@ constexpr int kMaxWavesPerCu = 12;
 
 constexpr int kStatSlots = 16;
 
+// The data-error counter and the optional FastGM counters of each device
+// live in static device memory (zero when the library is loaded), so that
+// setting up a device allocates nothing.
+static __device__ __align__(256) unsigned long long g_err_dev[1];
+static __device__ __align__(256) unsigned long long g_stats_dev[kStatSlots];
+
+// Scratch of gm_sketch_plain_noalloc: the partial registers and counters of
+// a split plain launch, in static device memory instead of a workspace.
+// kNoAllocRegs registers hold the split of one vector at any k (at most
+// 2048 workgroups of 256 registers); kNoAllocCounters bounds the (vector,
+// tile) pairs of a split launch.  In host code `scratch` names a host-side
+// stand-in: only the address hipGetSymbolAddress returns for it is used.
+constexpr int64_t kNoAllocRegs = 1ll << 19;
+constexpr int64_t kNoAllocCounters = 4096;
+constexpr size_t kNoAllocScratchBytes =
+    static_cast<size_t>(kNoAllocRegs) * (sizeof(double) + sizeof(int32_t)) +
+    2 * sizeof(int32_t) * static_cast<size_t>(kNoAllocCounters);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 struct DeviceState {
+  bool ready = false;
   unsigned long long* err = nullptr;
   unsigned long long* stats = nullptr;  // FastGM counters, when enabled
+  void* noalloc = nullptr;              // this device's address of `scratch`
   int cus = 0;
   std::map<hipStream_t, PlanWorkspace> plans;
 };
@@ -96,33 +117,33 @@ gm_status from_hip(hipError_t e) {
   return GM_ERR_DEVICE;
 }
 
-// Workspace of the current device (created on first use).
+// State of the current device, set up on first use: the device addresses of
+// the static counters and scratch (each device holds its own copies) and
+// the CU count.  Allocates nothing.
 gm_status device_state(DeviceState** out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return GM_ERR_DEVICE;
   if (dev < 0 || dev >= kMaxDevices) return GM_ERR_UNSUPPORTED;
   std::lock_guard<std::mutex> lock(g_mu);
   DeviceState& st = g_dev[dev];
-  if (!st.err) {
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sizeof(unsigned long long));
+  if (!st.ready) {
+    void* e_ptr = nullptr;
+    void* s_ptr = nullptr;
+    void* n_ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&e_ptr, HIP_SYMBOL(g_err_dev));
     if (e != hipSuccess) return from_hip(e);
-    e = hipMemset(p, 0, sizeof(unsigned long long));
-    if (e != hipSuccess) {
-      (void)hipFree(p);
-      return from_hip(e);
-    }
-    st.err = static_cast<unsigned long long*>(p);
-    void* q = nullptr;
-    e = hipMalloc(&q, sizeof(unsigned long long) * kStatSlots);
+    e = hipGetSymbolAddress(&s_ptr, HIP_SYMBOL(g_stats_dev));
     if (e != hipSuccess) return from_hip(e);
-    e = hipMemset(q, 0, sizeof(unsigned long long) * kStatSlots);
+    e = hipGetSymbolAddress(&n_ptr, HIP_SYMBOL(scratch));
     if (e != hipSuccess) return from_hip(e);
-    st.stats = static_cast<unsigned long long*>(q);
     hipDeviceProp_t prop;
     e = hipGetDeviceProperties(&prop, dev);
     if (e != hipSuccess) return from_hip(e);
+    st.err = static_cast<unsigned long long*>(e_ptr);
+    st.stats = static_cast<unsigned long long*>(s_ptr);
+    st.noalloc = n_ptr;
     st.cus = prop.multiProcessorCount;
+    st.ready = true;
   }
   *out = &st;
   return GM_OK;
@@ -210,7 +231,7 @@ gm_status sketch_common(const int32_t* indices, const float* weights, const int6
                         int64_t nvec, int32_t k_uniform, const int32_t* kvec,
                         const int64_t* outoff, int32_t k_max, uint64_t seed, gm_form form,
                         int32_t* out_idx, double* out_val, hipStream_t stream,
-                        int update = 0) {
+                        int update = 0, bool noalloc = false) {
   if (nvec < 0 || k_max < 1 || k_max > GM_K_MAX) return GM_ERR_INVALID_ARG;
   if (form != GM_FORM_FASTGM && form != GM_FORM_PLAIN) return GM_ERR_INVALID_ARG;
   if (nvec == 0) return GM_OK;
@@ -232,10 +253,15 @@ gm_status sketch_common(const int32_t* indices, const float* weights, const int6
   a.out_val = out_val;
   a.err = st->err;
   if (form == GM_FORM_PLAIN) {
-    void* scratch = nullptr;
-    s = plain_workspace(st, stream, &scratch);
-    if (s != GM_OK) return s;
-    return from_hip(gm::launch_plain(a, scratch, st->cus, stream));
+    gm::PlainScratch ps{nullptr, gm::plain_scratch_regs(st->cus),
+                        gm::plain_scratch_counters(st->cus), false};
+    if (noalloc) {
+      ps = gm::PlainScratch{st->noalloc, kNoAllocRegs, kNoAllocCounters, true};
+    } else {
+      s = plain_workspace(st, stream, &ps.base);
+      if (s != GM_OK) return s;
+    }
+    return from_hip(gm::launch_plain(a, ps, st->cus, stream));
   }
   if (nvec > 0x7FFFFFFF) return GM_ERR_UNSUPPORTED;
   PlanWorkspace* ws = nullptr;
@@ -275,6 +301,14 @@ gm_status gm_sketch_plain(const int32_t* indices, const float* weights, const in
                        GM_FORM_PLAIN, out_idx, out_val, stream);
 }
 
+gm_status gm_sketch_plain_noalloc(const int32_t* indices, const float* weights,
+                                  const int64_t* offsets, int64_t nvec, int32_t k, uint64_t seed,
+                                  int32_t* out_idx, double* out_val, hipStream_t stream) {
+  if (k < 1 || k > GM_K_MAX) return GM_ERR_INVALID_ARG;
+  return sketch_common(indices, weights, offsets, nvec, k, nullptr, nullptr, k, seed,
+                       GM_FORM_PLAIN, out_idx, out_val, stream, 0, true);
+}
+
 gm_status gm_sketch_batched(const int32_t* indices, const float* weights, const int64_t* offsets,
                             int64_t nvec, const int32_t* k_per_vec, const int64_t* out_offsets,
                             int32_t k_max, uint64_t seed, gm_form form, int32_t* out_idx,
@@ -292,8 +326,8 @@ gm_status gm_reserve(int64_t nvec, hipStream_t stream) {
   PlanWorkspace* ws = nullptr;
   s = plan_workspace(st, stream, nvec > 0 ? nvec : 1, &ws);
   if (s != GM_OK) return s;
-  void* scratch = nullptr;
-  return plain_workspace(st, stream, &scratch);
+  void* pscratch = nullptr;
+  return plain_workspace(st, stream, &pscratch);
 }
 
 gm_status gm_jaccard_est(const int32_t* idx_a, const int32_t* idx_b, int64_t npairs, int32_t k,
@@ -485,12 +519,8 @@ void gm_release(void) {
   (void)hipGetDevice(&cur);
   for (int d = 0; d < kMaxDevices; ++d) {
     DeviceState& st = g_dev[d];
-    if (!st.err && st.plans.empty()) continue;
+    if (st.plans.empty()) continue;
     (void)hipSetDevice(d);
-    if (st.err) (void)hipFree(st.err);
-    if (st.stats) (void)hipFree(st.stats);
-    st.err = nullptr;
-    st.stats = nullptr;
     for (auto& kv : st.plans) {
       if (kv.second.list) (void)hipFree(kv.second.list);
       if (kv.second.big) (void)hipFree(kv.second.big);

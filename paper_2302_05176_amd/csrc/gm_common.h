@@ -123,6 +123,16 @@ struct SketchArgs {
   unsigned long long* err;    // data-error counter
 };
 
+// Scratch handed to a plain-form launch for splitting vectors over
+// workgroups (see launch_plain): `regs` partial registers (8-byte values,
+// then 4-byte indices) followed by two arrays of `counters` int32.
+struct PlainScratch {
+  void* base;         // nullptr: the launch does not split
+  int64_t regs;
+  int64_t counters;
+  bool clear;         // zero the counters with a fill kernel before the launch
+};
+
 // Per-vector descriptor resolved on the device.
 struct VecDesc {
   int64_t a, b;   // entry range

@@ -183,23 +183,37 @@ int64_t plain_scratch_regs(int cus) {
 }
 int64_t plain_scratch_counters(int cus) { return static_cast<int64_t>(cus) * kPlainWgPerCu / 2 + 1; }
 
-// scratch: plain_scratch_regs(cus) x (8 + 4) bytes of partial registers,
-// then 2 x plain_scratch_counters(cus) int32 (zero on entry).
-hipError_t launch_plain(const SketchArgs& p, void* scratch, int cus, hipStream_t stream) {
+__global__ void zero_i32_kernel(int32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0;
+}
+
+// Scratch of a split launch: `regs` partial registers (8-byte values, then
+// 4-byte indices), then two arrays of `counters` int32.  With `clear`, the
+// counters the launch uses are zeroed by a fill kernel first; otherwise they
+// must be zero on entry (the kernel leaves them at zero).  A launch splits
+// only as far as the scratch holds; without scratch it does not split.
+hipError_t launch_plain(const SketchArgs& p, const PlainScratch& ps, int cus, hipStream_t stream) {
   const int tiles = (p.k_max + kPlainBlock - 1) / kPlainBlock;
   const int64_t target = static_cast<int64_t>(cus) * kPlainWgPerCu;
   PlainSplit sp{1, tiles, nullptr, nullptr, nullptr, nullptr};
   const int64_t pairs = p.nvec * tiles;
-  if (scratch && 2 * pairs < target) {
+  if (ps.base && 2 * pairs < target && pairs <= ps.counters) {
     int64_t parts = (target + pairs - 1) / pairs;
-    const int64_t regs = plain_scratch_regs(cus);
-    while (parts > 1 && p.nvec * parts * p.k_max > regs) --parts;
+    while (parts > 1 && p.nvec * parts * p.k_max > ps.regs) --parts;
     if (parts > 1) {
       sp.parts = static_cast<int32_t>(parts);
-      sp.part_val = static_cast<double*>(scratch);
-      sp.part_idx = reinterpret_cast<int32_t*>(sp.part_val + regs);
-      sp.count = sp.part_idx + regs;
-      sp.bad = sp.count + plain_scratch_counters(cus);
+      sp.part_val = static_cast<double*>(ps.base);
+      sp.part_idx = reinterpret_cast<int32_t*>(sp.part_val + ps.regs);
+      sp.count = sp.part_idx + ps.regs;
+      sp.bad = sp.count + ps.counters;
+      if (ps.clear) {
+        // (a fill kernel rather than a memset node: the call may be captured)
+        const int64_t n = ps.counters * 2;
+        hipLaunchKernelGGL(zero_i32_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                           stream, sp.count, n);
+      }
     }
   }
   const int64_t ntask = p.nvec * sp.parts;
