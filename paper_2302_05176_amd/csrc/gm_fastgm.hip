@@ -52,8 +52,10 @@
 //  * Exact indices on contest: walk again with the exact final y* and, for
 //    every arrival whose key equals its register's final key, atomic-min the
 //    element index into the register.
+#include <atomic>
 #include <cstddef>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -142,7 +144,8 @@ struct BigInfo {
   int64_t chunk_base;    // first chunk of this vector
   int64_t cand_off;      // offset of its candidate list in the pool
   double S;              // sum of weights: the slots added in order (by the probe pass)
-  int bad;               // invalid entry seen
+  int bad;               // invalid weight seen (sum pass)
+  int bad_index;         // negative index seen (probe pass; read after it)
   int cand_count;        // candidates found (may exceed cand_cap)
   int cand_cap;          // room in the pool (0: no list, walk everything)
   int parts_done;        // parts of a split walk that have written their sketch
@@ -1088,7 +1091,7 @@ __device__ bool sketch_vector(const FastArgs& fa, int64_t v, BigInfo* bi, FgShar
   if (bi) {
     if (tid == 0) {
       part = bi->S;
-      badl = bi->bad != 0;
+      badl = bi->bad != 0 || bi->bad_index != 0;
     }
   } else if (!bad0) {
     // four independent loads per lane in flight per step (the pass is
@@ -1417,7 +1420,7 @@ __device__ __forceinline__ void class_body(const FastArgs& fa) {
     if (fa.wave_lim > 0 && fa.s.off[v + 1] - fa.s.off[v] <= fa.wave_lim) break;
     BigInfo* bi = bigc ? &fa.big[plan->offset[fa.cls] - plan->offset[kBigFirst] + ti] : nullptr;
     int np = 1;
-    if (parts > 1 && !bi->bad && bi->S > 0.0 && bi->cand_cap > 0 &&
+    if (parts > 1 && !bi->bad && !bi->bad_index && bi->S > 0.0 && bi->cand_cap > 0 &&
         bi->cand_count <= bi->cand_cap) {
       const int want = bi->cand_count / kPartCand;
       np = want < 1 ? 1 : (want > parts ? parts : want);
@@ -1553,6 +1556,7 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t*
       bi.S = 0.0;
       for (int q = 0; q < kSumSlots; ++q) bi.Sslot[q] = 0.0;
       bi.bad = 0;
+      bi.bad_index = 0;
       bi.cand_count = 0;
       bi.cand_cap = (bi.cand_off + cap <= pool_cap) ? static_cast<int>(cap) : 0;
       bi.parts_done = 0;
@@ -1587,7 +1591,37 @@ __device__ __forceinline__ int big_of_chunk(const BigInfo* big, int c2, int64_t 
 
 constexpr int kBigBlock = 256;
 
-// Grid-wide pass 1 over big vectors: validate entries, sum weights.
+// Single-precision rejection of a first arrival.  The probe keeps an entry
+// when O_1 <= bound v, O_1 = RN(E_1 RN(1/k)) and E_1 = -ln u.  With
+// Y = k bound v log2(e): if u < 2^-Y - 2^-21, then -ln u exceeds k bound v by
+// at least 2^-21 (u <= 1), which the few ulp of the double-precision steps
+// cannot undo while k bound v < 2^28, so the exact test rejects the entry
+// too.  The test below implies that bound on u:
+//  * y = RN32(kbl v) with kbl >= k bound log2(e) (1 + 2^-18) gives y >= Y;
+//  * v_exp_f32 is accurate to 1 ulp, so exp2(-y) <= 2^-Y (1 + 2^-23), and
+//    q = exp2(-y) - 2^-20 < 2^-Y - 2^-21;
+//  * u <= (m + 1) 2^-24 with m the top 24 bits of the draw (u is
+//    ((x >> 11) + 1/2) 2^-53, rounded to nearest).
+// Where y is large (k bound v >= 2^28 included) exp2 underflows, q < 0 and
+// nothing is rejected; entries within 2^-20 of the boundary take the exact
+// path.
+__device__ __forceinline__ float rejection_scale(int k, double bound) {
+  const double want = static_cast<double>(k) * bound * 1.4426950408889634 * (1.0 + 0x1p-18);
+  float f = static_cast<float>(want);
+  if (static_cast<double>(f) < want) f = __uint_as_float(__float_as_uint(f) + 1u);  // round up
+  return f;
+}
+
+__device__ __forceinline__ bool surely_late(uint64_t x, float kbl, float v) {
+  const float y = kbl * v;
+  const float q = __builtin_amdgcn_exp2f(-y) - 0x1p-20f;
+  const float uhi = static_cast<float>(static_cast<uint32_t>(x >> 40) + 1u) * 0x1p-24f;
+  return uhi < q;
+}
+
+// Grid-wide pass 1 over big vectors: validate weights, sum them.  (Only the
+// weights are read here; the probe pass, which reads the indices anyway,
+// validates those.)
 __global__ __launch_bounds__(kBigBlock) void big_sum_kernel(FastArgs fa) {
   __shared__ double ws[kBigBlock / kWave];
   __shared__ int sbad;
@@ -1610,25 +1644,20 @@ __global__ __launch_bounds__(kBigBlock) void big_sum_kernel(FastArgs fa) {
     constexpr int kU = 16;
     int64_t e = e0 + tid;
     for (; e + (kU - 1) * kBigBlock < e1; e += kU * kBigBlock) {
-      int32_t iv[kU];
       float wv[kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        iv[u] = p.idx[e + u * kBigBlock];
-        wv[u] = p.w[e + u * kBigBlock];
-      }
+      for (int u = 0; u < kU; ++u) wv[u] = p.w[e + u * kBigBlock];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        if (iv[u] < 0 || !weight_valid(wv[u]))
+        if (!weight_valid(wv[u]))
           badl = true;
         else
           part += static_cast<double>(wv[u]);
       }
     }
     for (; e < e1; e += kBigBlock) {
-      const int32_t i = p.idx[e];
       const float wv = p.w[e];
-      if (i < 0 || !weight_valid(wv))
+      if (!weight_valid(wv))
         badl = true;
       else
         part += static_cast<double>(wv);
@@ -1668,7 +1697,17 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
     for (int q = 0; q < kSumSlots; ++q) S += bi->Sslot[q];
     // (every block of the vector computes the same S; later launches read it)
     if (tid == 0 && t == bi->chunk_base) bi->S = S;
-    if (d.bad || bi->bad || !(S > 0.0) || bi->cand_cap <= 0) continue;
+    if (d.bad || bi->bad) continue;  // poisoned already
+    if (!(S > 0.0) || bi->cand_cap <= 0) {
+      // no candidate list (no positive weight, or no room in the pool):
+      // only the indices are checked here
+      const int64_t e0 = d.a + (t - bi->chunk_base) * kBigChunk;
+      const int64_t e1 = e0 + kBigChunk < d.b ? e0 + kBigChunk : d.b;
+      bool badi = false;
+      for (int64_t e = e0 + tid; e < e1; e += kBigBlock) badi |= p.idx[e] < 0;
+      if (__ballot(badi) != 0 && lane == 0) atomicOr(&bi->bad_index, 1);
+      continue;
+    }
     double T0 = max_exp_quantile(d.k) * fa.t0_scale / S;
     if (fa.update) {
       // an update's walk stops at the stored sketch's largest register
@@ -1698,6 +1737,7 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
     // implies O_1 <= T0 v (1 + 2^-51.9); the test below, with two roundings
     // of its own, admits at least that and needs no division.
     const double bound = T0 * (1.0 + 0x1p-50);
+    const float kbl = rejection_scale(d.k, bound);
     const int64_t e0 = d.a + (t - bi->chunk_base) * kBigChunk;
     const int64_t e1 = e0 + kBigChunk < d.b ? e0 + kBigChunk : d.b;
     // The chunk's candidates are gathered in LDS and the vector's list takes
@@ -1705,6 +1745,7 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
     // serialise the pass.
     if (tid == 0) scount = 0;
     __syncthreads();
+    bool badl = false;
     // four entries per lane per step, their loads issued together
     constexpr int kPU = 4;
     for (int64_t eb = e0; eb < e1; eb += kPU * kBigBlock) {
@@ -1720,10 +1761,15 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
       for (int u = 0; u < kPU; ++u) {
         const int64_t e = eb + u * kBigBlock + tid;
         bool cand = false;
+        if (iv[u] < 0) badl = true;
         if (wv[u] > 0.0f) {
           const uint64_t P = mix(p.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(iv[u])));
-          const double O1 = fma(exp1(draw(P, kTagArrival, 1u)), c1, 0.0);
-          cand = O1 <= bound * static_cast<double>(wv[u]);
+          const uint64_t x = draw(P, kTagArrival, 1u);
+          // most entries are rejected in single precision, without the log
+          if (!surely_late(x, kbl, wv[u])) {
+            const double O1 = fma(exp1(x), c1, 0.0);
+            cand = O1 <= bound * static_cast<double>(wv[u]);
+          }
         }
         const uint64_t m = __ballot(cand);
         if (m) {
@@ -1736,6 +1782,9 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
         }
       }
     }
+    // a negative index poisons the vector (the walk reads the flag; this
+    // pass never does, so its blocks take the same branches)
+    if (__ballot(badl) != 0 && lane == 0) atomicOr(&bi->bad_index, 1);
     __syncthreads();
     const int nc = scount;
     if (tid == 0 && nc > 0) sbase = atomicAdd(&bi->cand_count, nc);
@@ -1775,8 +1824,10 @@ struct TimedLaunch {
   hipEvent_t a, b;
 };
 
+// Shared by every host thread that launches: one mutex guards the lists.
 struct TimingState {
-  int level = 0;  // 0 off, 1 every launch, 2 the sketch kernels only
+  std::atomic<int> level{0};  // 0 off, 1 every launch, 2 the sketch kernels only
+  std::mutex mu;
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> free_events;
   std::vector<std::string> names;
@@ -1819,6 +1870,7 @@ static hipEvent_t timing_event() {
 static int timing_begin(const char* name, bool main, hipStream_t stream, hipEvent_t* a) {
   const int level = timing().level;
   if (level == 0 || (level == 2 && !main)) return -1;
+  std::lock_guard<std::mutex> lock(timing().mu);
   *a = timing_event();
   (void)hipEventRecord(*a, stream);
   return timing_id(name);
@@ -1826,6 +1878,7 @@ static int timing_begin(const char* name, bool main, hipStream_t stream, hipEven
 
 static void timing_end(int id, hipEvent_t a, hipStream_t stream) {
   if (id < 0) return;
+  std::lock_guard<std::mutex> lock(timing().mu);
   hipEvent_t b = timing_event();
   (void)hipEventRecord(b, stream);
   timing().pending.push_back(TimedLaunch{id, a, b});
@@ -1834,6 +1887,7 @@ static void timing_end(int id, hipEvent_t a, hipStream_t stream) {
 // Sum the finished launches; copy up to n (name, total ms, launches).
 int timing_collect(int n, char (*names)[64], double* ms, long long* launches) {
   TimingState& t = timing();
+  std::lock_guard<std::mutex> lock(t.mu);
   for (TimedLaunch& l : t.pending) {
     (void)hipEventSynchronize(l.b);
     float m = 0.0f;
@@ -1857,6 +1911,7 @@ int timing_collect(int n, char (*names)[64], double* ms, long long* launches) {
 void timing_reset() {
   TimingState& t = timing();
   (void)timing_collect(0, nullptr, nullptr, nullptr);
+  std::lock_guard<std::mutex> lock(t.mu);
   t.names.clear();
   t.total_ms.clear();
   t.launches.clear();
@@ -1879,20 +1934,25 @@ static hipError_t launch_class(const FastArgs& fa, int cus, hipStream_t stream) 
   const bool big = fa.cls >= kBigFirst;
   const void* fn = big ? reinterpret_cast<const void*>(fastgm_big_kernel<W, G>)
                        : reinterpret_cast<const void*>(fastgm_class_kernel<W, G>);
-  // occupancy per (kernel, LDS size), computed once
+  // occupancy per (kernel, LDS size), computed once (guarded: several host
+  // threads may launch)
   static OccKey cache[64];
   static int ncache = 0;
+  static std::mutex cache_mu;
   int per_cu = 0;
-  for (int i = 0; i < ncache; ++i)
-    if (cache[i].fn == fn && cache[i].lds == lds) per_cu = cache[i].per_cu;
-  if (per_cu == 0) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(lds));
-    if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, W * kWave, lds);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    if (ncache < 64) cache[ncache++] = OccKey{fn, lds, per_cu};
+  {
+    std::lock_guard<std::mutex> lock(cache_mu);
+    for (int i = 0; i < ncache; ++i)
+      if (cache[i].fn == fn && cache[i].lds == lds) per_cu = cache[i].per_cu;
+    if (per_cu == 0) {
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         static_cast<int>(lds));
+      if (e != hipSuccess) return e;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, W * kWave, lds);
+      if (e != hipSuccess) return e;
+      if (per_cu < 1) per_cu = 1;
+      if (ncache < 64) cache[ncache++] = OccKey{fn, lds, per_cu};
+    }
   }
   int64_t grid = static_cast<int64_t>(cus) * per_cu;
   // tasks: one per vector, or up to kMaxParts per big vector

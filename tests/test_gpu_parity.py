@@ -144,6 +144,38 @@ def test_poisoned_vectors_and_error_counter(gm):
     assert gm.get_data_errors() == 0
 
 
+def test_big_vector_poison(gm):
+    """Vectors above the 32768-entry limit are validated by the grid-wide
+    passes: a negative index (found by the probe pass) or a NaN weight (the
+    sum pass) poisons only its own vector; the clean big vector beside them,
+    whose probe rejects most entries in single precision, equals the oracle."""
+    rng = np.random.default_rng(404)
+    rows_i, rows_w = [], []
+    for v in range(3):
+        n = 40_000 + 1000 * v
+        rows_i.append(rng.choice(1 << 24, size=n, replace=False).astype(np.int32))
+        rows_w.append(rng.exponential(1.0, size=n).astype(np.float32) + np.float32(1e-3))
+    rows_i[1][20_000] = -5
+    rows_w[2][33_333] = np.nan
+    # no positive weight: with a negative index poisoned, without it empty
+    for v in (3, 4):
+        rows_i.append(rng.choice(1 << 24, size=36_000, replace=False).astype(np.int32))
+        rows_w.append(np.zeros(36_000, np.float32))
+    rows_i[3][35_999] = -1
+    idx, w, off = W._pack(rows_i, rows_w)
+    gm.reset_data_errors()
+    for k in (64, 1024):
+        print(f"big vectors with a bad index / NaN weight / no weight, k={k}", flush=True)
+        got = _gpu_sketch(gm, idx, w, off, k, 8)
+        want = oracle.sketch(idx, w, off, k, 8, form=oracle.FORM_STREAM)
+        assert np.all(got[0][1:4] == -2) and np.all(np.isnan(got[1][1:4]))
+        assert np.all(got[0][4] == -1) and np.all(np.isinf(got[1][4]))
+        _assert_same((got[0][:1], got[1][:1]), (want[0][:1], want[1][:1]), f"clean k={k}")
+        assert np.array_equal(got[0], want[0])
+    assert gm.get_data_errors() == 6
+    gm.reset_data_errors()
+
+
 def test_empty_inputs(gm):
     # nvec = 0: nothing launched
     z = torch.zeros(0, dtype=torch.int32, device=DEV)
