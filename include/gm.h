@@ -173,6 +173,17 @@ gm_status gm_sketch_batched(const int32_t *indices, const float *weights, const 
 gm_status gm_reserve(int64_t nvec, hipStream_t stream);
 
 /*
+ * gm_workspace_bytes -- device bytes of the workspace that gm_reserve(nvec,
+ * stream) creates for one stream on the current device: the FastGM planner
+ * list and per-vector records (about 200 bytes per vector), the big-vector
+ * candidate pool (128 MiB), the walk's per-wave lists (64 KiB per resident
+ * wave), the split-walk scratch and the plain form's split scratch.  For
+ * admission control: each stream that sketches concurrently holds one.
+ * Allocates nothing; nvec in [0, 2^31).
+ */
+gm_status gm_workspace_bytes(int64_t nvec, int64_t *bytes);
+
+/*
  * gm_jaccard_est -- probability-Jaccard estimate of Sec. 1:
  *   out[p] = #{ j : a[p*k+j] == b[p*k+j] and a[p*k+j] >= 0 } / k
  * for npairs row-major pairs of Gumbel-ArgMax sketches (Theorem 1: unbiased
@@ -399,7 +410,11 @@ gm_status gm_autotune(const int32_t *indices, const float *weights, const int64_
  * start (0).  Up to config.slots batches are in flight, one HIP stream each;
  * a free slot admits pending requests in arrival order while the batch holds
  * at most max_batch_requests requests and max_batch_entries sketch entries
- * and the in-flight device bytes stay within device_budget_bytes; a partial
+ * and the in-flight device bytes stay within device_budget_bytes.  A busy
+ * slot counts its staging buffers plus its stream's library workspace
+ * (gm_workspace_bytes(max_batch_requests)); fewer slots than asked are used
+ * when the budget holds fewer, and a budget below one slot is an argument
+ * error.  A partial
  * batch waits for more requests until its oldest one has waited max_wait_us
  * (0: it launches at once; while every slot is busy, arrivals accumulate and
  * the next free slot takes them together).
@@ -435,6 +450,8 @@ typedef struct {
     int64_t batches, sketch_requests, jaccard_requests, entries;
     int64_t max_inflight_bytes, max_slots_busy, slots;
     double wall_us;
+    int64_t slot_bytes;       /* device bytes one busy slot counts: staging + workspace */
+    int64_t workspace_bytes;  /* of which the slot stream's library workspace */
 } gm_serve_stats;
 gm_status gm_serve_run(const gm_serve_config *cfg, const gm_request *reqs, int64_t nreq,
                        const int32_t *host_idx, const float *host_w,

@@ -294,6 +294,14 @@ def reserve(nvec: int, stream=None) -> None:
     _native.check(_native.load().gm_reserve(int(nvec), _stream(stream)), "gm_reserve")
 
 
+def workspace_bytes(nvec: int) -> int:
+    """Device bytes of one stream's library workspace for calls of up to nvec
+    vectors (gm_workspace_bytes)."""
+    n = ctypes.c_int64(0)
+    _native.check(_native.load().gm_workspace_bytes(int(nvec), ctypes.byref(n)), "gm_workspace_bytes")
+    return int(n.value)
+
+
 def get_data_errors(stream=None) -> int:
     L = _native.load()
     n = ctypes.c_int64(0)

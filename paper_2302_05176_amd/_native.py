@@ -80,6 +80,7 @@ def load() -> ctypes.CDLL:
     L.gm_status_string.argtypes = [ctypes.c_int]
     L.gm_status_string.restype = ctypes.c_char_p
     L.gm_reserve.argtypes = [i64, p]
+    L.gm_workspace_bytes.argtypes = [i64, ctypes.POINTER(ctypes.c_int64)]
     L.gm_serve_run.argtypes = [p, p, i64, p, p, p, i64, p, p, p, p, p]
     L.gm_autotune.argtypes = [p, p, p, i64, p, p, i32, u64, p, p, i32, i32,
                               ctypes.POINTER(TuneResult), p]
@@ -95,7 +96,7 @@ def load() -> ctypes.CDLL:
     L.gm_release.restype = None
     for name in ("gm_sketch", "gm_sketch_plain", "gm_sketch_plain_noalloc", "gm_sketch_batched", "gm_jaccard_est",
                  "gm_jaccard_est_pairs", "gm_wcard_est", "gm_merge", "gm_setops", "gm_get_data_errors",
-                 "gm_reset_data_errors", "gm_set_option", "gm_get_stats", "gm_reset_stats", "gm_reserve", "gm_autotune",
+                 "gm_reset_data_errors", "gm_set_option", "gm_get_stats", "gm_reset_stats", "gm_reserve", "gm_workspace_bytes", "gm_autotune",
                  "gm_serve_run", "gm_lsh_build", "gm_lsh_query", "gm_lsh_info"):
         getattr(L, name).restype = st
     _lib = L

@@ -4,6 +4,7 @@
 // error), the per-device workspace (data-error counter), process-wide tuning
 // options, and dispatch to the kernel launchers.  No call allocates on the
 // steady-state path: the workspace is created by the first call on a device.
+#include <atomic>
 #include <map>
 #include <mutex>
 
@@ -102,14 +103,18 @@ struct DeviceState {
 std::mutex g_mu;
 DeviceState g_dev[kMaxDevices];
 
-// Tuning / testing options (process-wide).
-int g_pos_bits = 24;
-double g_t0_scale = 1.0;
-int g_map_load = 14;
-int g_republish = 8;
-double g_seg_rest = 12.0;
-int g_small_waves = 0;
-bool g_stats = false;
+// Tuning / testing options (process-wide).  Each is read once per call, as
+// an atomic, so a gm_set_option from another host thread (the autotuner
+// beside a serving loop, say) takes effect from some call on and never
+// tears a value; a call sees a mix of old and new options only while a
+// change is under way.
+std::atomic<int> g_pos_bits{24};
+std::atomic<double> g_t0_scale{1.0};
+std::atomic<int> g_map_load{14};
+std::atomic<int> g_republish{8};
+std::atomic<double> g_seg_rest{12.0};
+std::atomic<int> g_small_waves{0};
+std::atomic<bool> g_stats{false};
 
 gm_status from_hip(hipError_t e) {
   if (e == hipSuccess) return GM_OK;
@@ -328,6 +333,21 @@ gm_status gm_reserve(int64_t nvec, hipStream_t stream) {
   if (s != GM_OK) return s;
   void* pscratch = nullptr;
   return plain_workspace(st, stream, &pscratch);
+}
+
+gm_status gm_workspace_bytes(int64_t nvec, int64_t* bytes) {
+  if (!bytes || nvec < 0 || nvec > 0x7FFFFFFF) return GM_ERR_INVALID_ARG;
+  DeviceState* st = nullptr;
+  gm_status s = device_state(&st);
+  if (s != GM_OK) return s;
+  const int64_t n = nvec > 0 ? nvec : 1;
+  const int64_t waves = static_cast<int64_t>(st->cus) * kMaxWavesPerCu;
+  *bytes = static_cast<int64_t>(gm::plan_state_bytes()) +
+           static_cast<int64_t>(sizeof(int32_t)) * kPoolCap + waves * gm::heavy_list_bytes() +
+           static_cast<int64_t>(gm::part_scratch_bytes()) +
+           n * static_cast<int64_t>(sizeof(int32_t) + gm::big_info_bytes()) +
+           static_cast<int64_t>(plain_scratch_bytes(st->cus));
+  return GM_OK;
 }
 
 gm_status gm_jaccard_est(const int32_t* idx_a, const int32_t* idx_b, int64_t npairs, int32_t k,

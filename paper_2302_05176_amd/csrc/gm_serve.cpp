@@ -6,7 +6,8 @@
 // loop keeps `slots` batches in flight, one HIP stream each, and whenever a
 // slot is free it admits pending requests in arrival order while the batch
 // stays within its entry and request limits and the in-flight device bytes
-// stay within the budget.  A partial batch is launched once its oldest
+// (each busy slot's staging buffers and its stream's library workspace) stay
+// within the budget.  A partial batch is launched once its oldest
 // request has waited `max_wait_us` (or when nothing else can arrive).  Each
 // batch stages its sketch requests' entries in pinned memory, copies them to
 // the slot's device buffers, sketches them with gm_sketch (FastGM form), and
@@ -129,9 +130,18 @@ extern "C" gm_status gm_serve_run(const gm_serve_config* cfg, const gm_request* 
     for (int64_t r = 0; r < nreq; ++r)
       if (reqs[r].kind == GM_REQ_SKETCH) sk_row[r] = i++;
   }
-  // one slot's device footprint (what the budget counts per batch in flight)
+  // One slot's device footprint, what the budget counts per batch in flight:
+  // its staging buffers (entries, offsets, outputs, query pairs and answers)
+  // and the library workspace its stream holds for sketch calls of up to R
+  // vectors.  (LDS needs no admission: each launch sizes its grid to what the
+  // CUs hold, and launches from several slots queue for the CUs.)
+  int64_t ws_bytes = 0;
+  {
+    const gm_status g = gm_workspace_bytes(R, &ws_bytes);
+    if (g != GM_OK) return g;
+  }
   const int64_t slot_bytes =
-      E * 8 + (R + 1) * 8 + R * k * 12 + R * (8 + 8 + 8);
+      E * 8 + (R + 1) * 8 + R * k * 12 + R * (8 + 8 + 8) + ws_bytes;
   if (slot_bytes > cfg->device_budget_bytes) return GM_ERR_INVALID_ARG;  // not even one batch fits
   int nslots = cfg->slots;
   if (nslots * slot_bytes > cfg->device_budget_bytes)
@@ -320,6 +330,8 @@ extern "C" gm_status gm_serve_run(const gm_serve_config* cfg, const gm_request* 
   }
   st.wall_us = now_us();
   st.slots = nslots;
+  st.slot_bytes = slot_bytes;
+  st.workspace_bytes = ws_bytes;
   for (Slot& s : slots) free_slot(s);
   if (stats) *stats = st;
   return status;

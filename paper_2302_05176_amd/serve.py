@@ -35,7 +35,8 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_int64), ("sketch_requests", ctypes.c_int64),
                 ("jaccard_requests", ctypes.c_int64), ("entries", ctypes.c_int64),
                 ("max_inflight_bytes", ctypes.c_int64), ("max_slots_busy", ctypes.c_int64),
-                ("slots", ctypes.c_int64), ("wall_us", ctypes.c_double)]
+                ("slots", ctypes.c_int64), ("wall_us", ctypes.c_double),
+                ("slot_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
 
 
 def make_trace(nreq: int, rate: float, nstore: int, seed: int = 1005, sketch_every: int = 5,

@@ -30,13 +30,17 @@ def test_serving_results_same_alone_and_in_the_mix():
     from paper_2302_05176_amd import serve
     k, nstore = 128, 3000
     store = serve.build_store(nstore, k)
-    reqs, hi, hw = serve.make_trace(400, rate=20_000.0, nstore=nstore, size_mu=np.log(300.0),
+    # arrivals faster than a batch completes: requests queue while others run
+    reqs, hi, hw = serve.make_trace(400, rate=400_000.0, nstore=nstore, size_mu=np.log(300.0),
                                     size_sigma=1.0, size_cap=20_000)
     res = serve.run(reqs, hi, hw, store, k, seed=7, slots=4, max_batch_requests=32,
-                    max_wait_us=100.0, want_sketches=True)
+                    max_wait_us=0.0, want_sketches=True, device_budget_bytes=8 << 30)
     st = res["stats"]
     assert st["sketch_requests"] + st["jaccard_requests"] == len(reqs)
-    assert st["batches"] > 1 and st["max_slots_busy"] >= 1
+    # batches overlapped on the device, and batches held several requests
+    assert st["max_slots_busy"] >= 2, st
+    assert 1 < st["batches"] < len(reqs), st
+    assert st["max_inflight_bytes"] <= 8 << 30
     assert np.all(res["latency_us"] > 0)
     sk = np.nonzero(reqs["kind"] == serve.SKETCH)[0]
     # alone: every sketch request on its own
@@ -61,3 +65,33 @@ def test_serving_results_same_alone_and_in_the_mix():
         assert res["jaccard"][r] == want, f"query {r}"
     summ = serve.summarize(reqs, res)
     assert summ["p99_us"] >= summ["p50_us"] > 0
+
+
+def test_serving_admission_counts_the_workspace():
+    """The device budget bounds what is in flight, the library workspace of
+    each slot stream included: with room for two slots only, at most two
+    batches run at once and the in-flight bytes stay within the budget."""
+    import paper_2302_05176_amd as gm
+    from paper_2302_05176_amd import serve
+    k, nstore = 64, 500
+    store = serve.build_store(nstore, k)
+    reqs, hi, hw = serve.make_trace(300, rate=400_000.0, nstore=nstore, size_mu=np.log(200.0),
+                                    size_sigma=0.5, size_cap=2_000)
+    R = 16
+    ws = gm.workspace_bytes(R)
+    assert ws > 128 << 20          # the candidate pool alone is 128 MiB
+    probe = serve.run(reqs[:5], hi, hw, store, k, seed=3, slots=1, max_batch_requests=R,
+                      max_batch_entries=1 << 14, device_budget_bytes=64 << 30)
+    slot = probe["stats"]["slot_bytes"]
+    assert probe["stats"]["workspace_bytes"] == ws and slot > ws
+    budget = 2 * slot + slot // 2
+    res = serve.run(reqs, hi, hw, store, k, seed=3, slots=6, max_batch_requests=R,
+                    max_batch_entries=1 << 14, device_budget_bytes=budget)
+    st = res["stats"]
+    assert st["slots"] == 2, st
+    assert st["max_slots_busy"] <= 2 and st["max_inflight_bytes"] <= budget, st
+    assert st["sketch_requests"] + st["jaccard_requests"] == len(reqs)
+    # a budget below one slot is refused
+    with pytest.raises(gm.GMError):
+        serve.run(reqs[:5], hi, hw, store, k, seed=3, slots=1, max_batch_requests=R,
+                  max_batch_entries=1 << 14, device_budget_bytes=slot - 1)
