@@ -65,6 +65,58 @@ def harmonic(k: int) -> float:
     return sum(1.0 / m for m in range(1, k + 1))
 
 
+def max_exp_quantile(k: int, p: float) -> float:
+    """(1 - p) quantile of the maximum of k Exp(1) variables (Sec. 2.5)."""
+    import math
+    return -math.log(-math.expm1(math.log1p(-p) / k))
+
+
+def rate_ceiling(k: int, seed: int = 1) -> float:
+    """Arrivals/s of gm_rate_probe at this k: 2^21 lanes, each drawing k
+    arrivals of its own element with no memory traffic -- the ceiling of the
+    arrival arithmetic as compiled."""
+    import torch
+
+    import paper_2302_05176_amd as gm
+    lanes = 1 << 21
+    out = torch.empty(lanes, dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    ms, _ = timed_steps(lambda: gm.rate_probe("arrivals", lanes, k, seed, out=out), 3, 1, stream)
+    return lanes * k / (ms / 1e3)
+
+
+def kernel_roofline(name, ms, units=None, slots=None, unit_name=None, hbm_bytes=None,
+                    bound="alu", ceiling=None, traffic=None):
+    """Roofline entry of one kernel from its average launch duration (ms):
+    ALU-bound entries count algorithmic units x issue slots against the VALU
+    peak; HBM-bound ones algorithmic bytes against 8 TB/s."""
+    sec = ms / 1e3
+    e = {"kernel": name, "kernel_ms": ms, "bound": bound}
+    if bound == "alu":
+        ach = units * slots / sec
+        e.update({"achieved": ach / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s",
+                  "op": "f64-rate VALU lane-cycle (algorithmic units x slots per unit)",
+                  "frac": ach / PEAK_VALU_OPS, "algorithmic_units": units, "unit_name": unit_name,
+                  "slots_per_unit": slots})
+        if ceiling:
+            e["arrivals_per_s"] = units / sec
+            e["probe_ceiling_arrivals_per_s"] = ceiling
+            e["frac_of_probe"] = units / sec / ceiling
+    else:
+        e.update({"achieved": hbm_bytes / sec / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                  "frac": hbm_bytes / sec / HBM_PEAK})
+    if hbm_bytes is not None:
+        e["algorithmic_bytes"] = hbm_bytes
+        e["hbm_algorithmic_frac"] = hbm_bytes / sec / HBM_PEAK
+    e["traffic"] = traffic
+    return e
+
+
+def per_kernel_ms(timing):
+    """{name: average ms per launch} from gm.get_timing()."""
+    return {n: t / c for n, (t, c) in timing.items() if c}
+
+
 # Sources that build the measured sketch kernels or set their launch
 # parameters: a change to their code (comments and spacing aside) makes
 # committed counters stale.
@@ -207,8 +259,14 @@ def timed_steps(fn, steps, warmup, stream):
 
 def cpu_baseline(idx, w, off, k, seed, seconds, form):
     import oracle
-    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    ncores = max(1, min(ncores, 16))
+    # every core of the affinity mask, but no more than OMP_NUM_THREADS when
+    # the environment sets it (a host shared by several GPUs gives each GPU's
+    # jobs a share of its cores that way)
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    ncores = affinity
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit() and int(os.environ["OMP_NUM_THREADS"]) > 0:
+        ncores = min(ncores, int(os.environ["OMP_NUM_THREADS"]))
+    ncores = max(1, ncores)
     oracle.set_threads(ncores)
     nvec = len(off) - 1
     f = oracle.FORM_STREAM if form == "fastgm" else oracle.FORM_PLAIN
@@ -222,7 +280,8 @@ def cpu_baseline(idx, w, off, k, seed, seconds, form):
         if dt >= seconds:
             break
     what = ("Algorithm 2 (Stream-FastGM)" if form == "fastgm" else "plain O(k n+)")
-    return {"value": done * nv * k / dt, "unit": "registers/s", "cores": ncores, "kind": "oracle",
+    return {"value": done * nv * k / dt, "unit": "registers/s", "cores": ncores,
+            "affinity_cores": affinity, "kind": "oracle",
             "sample": f"{what} over the first {nv} vectors of the batch, {done} pass(es) with "
                       f"different seeds, {dt:.1f} s wall on {ncores} threads"}
 
@@ -289,25 +348,12 @@ def bench_batch(args):
         unit_name = "keys (k n+)"
         vec_bytes = 8.0 * nnz + 8.0 * (args.nvec + 1) + 12.0 * regs
     tot_ms, launches = kt.get(key if args.form == "fastgm" else kern, (0.0, 0))
-    kern_s = tot_ms / launches / 1e3 if launches else ev_ms / 1e3
-    achieved = units * slots / kern_s
+    kern_ms = tot_ms / launches if launches else ev_ms
     traffic = committed_traffic(kern, f"batch_k{k}_{args.form}")
-    roofline = {
-        "bound": "alu",
-        "achieved": achieved / 1e12,
-        "peak": PEAK_VALU_OPS / 1e12,
-        "unit": "TOP/s",
-        "op": "f64-rate VALU lane-cycle (algorithmic units x slots per unit)",
-        "frac": achieved / PEAK_VALU_OPS,
-        "traffic": traffic,
-        "kernel": kern,
-        "kernel_ms": kern_s * 1e3,
-        "algorithmic_units": units,
-        "unit_name": unit_name,
-        "slots_per_unit": slots,
-        "hbm_algorithmic_frac": vec_bytes / kern_s / HBM_PEAK,
-        "kernels_ms_per_step": breakdown,
-    }
+    ceiling = rate_ceiling(k, args.seed) if args.form == "fastgm" else None
+    roofline = kernel_roofline(kern, kern_ms, units, slots, unit_name, vec_bytes, "alu", ceiling,
+                               traffic)
+    roofline["kernels_ms_per_step"] = breakdown
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(idx, w, off, k, args.seed, args.cpu_seconds, args.form)
@@ -380,34 +426,80 @@ def bench_single(args):
                       "results": res}), flush=True)
 
 
+def stream_kernel_rooflines(breakdown, n, k):
+    """Roofline entries of the kernels of one stream-vector sketch (n entries,
+    one vector of more than 32768 entries): the weight sum (4 bytes per
+    entry), the probe (index and weight, 8 bytes per entry: with the
+    single-precision rejection it is meant to run at the HBM line) and the
+    candidate walk (k H_k arrivals beyond the first ones)."""
+    ent = {}
+    for name, ms in breakdown.items():
+        if name.startswith("big_sum_kernel"):
+            ent[name] = kernel_roofline(name, ms, hbm_bytes=4.0 * n, bound="hbm")
+        elif name.startswith("big_probe_kernel"):
+            ent[name] = kernel_roofline(name, ms, hbm_bytes=8.0 * n, bound="hbm")
+        elif name.startswith("fastgm_big_kernel"):
+            ent[name] = kernel_roofline(name, ms, k * harmonic(k), ARRIVAL_SLOTS,
+                                        "arrivals (k H_k beyond the first arrivals)",
+                                        hbm_bytes=12.0 * k, bound="alu")
+    return ent
+
+
 def bench_stream(args):
+    """One vector of 10^7 entries, k = 1024 and 4096.  The headline of the
+    line is k = 1024; each k reports its step time, the per-kernel roofline
+    entries (HIP events around every launch, on the call's stream, inside the
+    timed loop), the cardinality estimator over 100 seeds, and the plain
+    form's time for the FastGM/plain ratio."""
+    import numpy as np
     import torch
 
     import paper_2302_05176_amd as gm
     from paper_2302_05176_amd import workloads as W
     dev = torch.device("cuda:0")
     idx, w, off = W.stream(nplus=10_000_000)
+    n = int(off[-1])
     ti, tw, to = (torch.from_numpy(a).to(dev) for a in (idx, w, off))
     stream = torch.cuda.current_stream()
     S = float(w.astype("float64").sum())
     out = {}
     for k in (1024, 4096):
-        ms, _ = timed_steps(lambda: gm.sketch(ti, tw, to, k, args.seed), args.steps, args.warmup,
-                            stream)
+        step = lambda kk=k: gm.sketch(ti, tw, to, kk, args.seed)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        gm.set_option("timing", 1)
+        gm.reset_timing()
+        ms, _ = timed_steps(step, args.steps, 0, stream)
+        breakdown = per_kernel_ms(gm.get_timing())
+        gm.set_option("timing", 0)
+        kern = stream_kernel_rooflines(breakdown, n, k)
+        dom = max(kern.values(), key=lambda e: e["kernel_ms"])
         ests = []
         for seed in range(1, 101):
             _, y = gm.sketch(ti, tw, to, k, seed)
             ests.append(float(gm.wcard_est(y).item()))
-        import numpy as np
         r = np.array(ests) / S
         out[f"k{k}"] = {"ms_per_sketch": ms, "registers_per_s": k / (ms / 1e3),
-                        "entries_per_s": 1e7 / (ms / 1e3),
-                        "wcard_mean_ratio": float(r.mean()), "wcard_rel_var_x_(k-2)": float(r.var(ddof=1) * (k - 2))}
-    pms, _ = timed_steps(lambda: gm.sketch(ti, tw, to, 1024, args.seed, form="plain"), 1, 0, stream)
+                        "entries_per_s": n / (ms / 1e3), "roofline": dom, "kernels": kern,
+                        "kernels_ms_per_step": breakdown,
+                        "wcard_mean_ratio": float(r.mean()),
+                        "wcard_rel_var_x_(k-2)": float(r.var(ddof=1) * (k - 2))}
+    pms, _ = timed_steps(lambda: gm.sketch(ti, tw, to, 1024, args.seed, form="plain"), 3, 1, stream)
     out["plain_k1024_ms"] = pms
+    out["plain_k1024_roofline"] = kernel_roofline("plain_kernel", pms, 1024.0 * n, PLAIN_KEY_SLOTS,
+                                                  "keys (k n+)", 8.0 * n + 16 + 12 * 1024, "alu")
     out["speedup_vs_plain_k1024"] = pms / out["k1024"]["ms_per_sketch"]
-    print(json.dumps({"workload": "one stream vector n+=1e7, half Uniform(0,1], half 1+Pareto(1.5)",
-                      "results": out}), flush=True)
+    head = out["k1024"]
+    print(json.dumps({"metric": "Gumbel-Max registers/sec (FastGM form, one 10^7-entry vector, k=1024)",
+                      "value": head["registers_per_s"], "unit": "registers/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_sketch"],
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                      "data": "synthetic",
+                      "config": {"workload": "one stream vector n+=1e7, indices distinct in [0, 2^31-1), "
+                                             "half Uniform(0,1], half 1+Pareto(1.5) fp32 weights, "
+                                             "k=1024 (k=4096 in results)"},
+                      "roofline": head["roofline"], "results": out}), flush=True)
 
 
 def bench_stream_update(args):
@@ -450,6 +542,41 @@ def bench_stream_update(args):
           flush=True)
 
 
+def uneven_kernel_rooflines(breakdown, n, kk):
+    """Roofline entries of the launches of a mixed-k batch.  A class kernel
+    drains the vectors of at most 32768 entries of one k range: k H_k + n+
+    arrivals per vector; bytes 8 n+ + 8 + 12 k + 12 (k and output offset).
+    Big vectors (more than 32768 entries): the sum pass reads 4 bytes and the
+    probe 8 bytes per entry; their walk kernel draws k H_k arrivals per
+    vector beyond the first ones."""
+    import numpy as np
+    kcls = np.where(kk <= 256, 0, np.where(kk <= 1024, 1, np.where(kk <= 2048, 2, 3)))
+    hk = {int(k): harmonic(int(k)) for k in np.unique(kk)}
+    hv = np.array([hk[int(k)] for k in kk])
+    small = n <= SMALL_LIMIT
+    ent = {}
+    for name, ms in breakdown.items():
+        if name.startswith("big_sum_kernel"):
+            ent[name] = kernel_roofline(name, ms, hbm_bytes=4.0 * n[~small].sum(), bound="hbm")
+        elif name.startswith("big_probe_kernel"):
+            ent[name] = kernel_roofline(name, ms, hbm_bytes=8.0 * n[~small].sum(), bound="hbm")
+        elif "[class " in name:
+            c = int(name.split("class ")[1].rstrip("]"))
+            sel = (kcls == c % 4) & (small if c < 4 else ~small)
+            if not sel.any():
+                continue
+            if c < 4:
+                units = float((kk[sel] * hv[sel]).sum() + n[sel].sum())
+                uname = "arrivals (k H_k + n+ per vector of the class)"
+                byt = 8.0 * n[sel].sum() + 8.0 * (sel.sum() + 1) + 12.0 * kk[sel].sum() + 12.0 * sel.sum()
+            else:
+                units = float((kk[sel] * hv[sel]).sum())
+                uname = "arrivals (k H_k per big vector, beyond the first arrivals)"
+                byt = 12.0 * kk[sel].sum() + 12.0 * sel.sum()
+            ent[name] = kernel_roofline(name, ms, units, ARRIVAL_SLOTS, uname, byt, "alu")
+    return ent
+
+
 def bench_uneven(args):
     import numpy as np
     import torch
@@ -480,11 +607,35 @@ def bench_uneven(args):
                           stream=torch.cuda.current_stream())
     torch.cuda.synchronize()
     ms, _ = timed_steps(lambda: g.replay(), max(2, args.steps // 4), 1, torch.cuda.current_stream())
+    # Per-kernel durations: the captured graph holds no timing events, so the
+    # same call (same options) runs eagerly with HIP events around every
+    # launch on its stream.
+    gm.set_option("timing", 1)
+    gm.reset_timing()
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            gm.sketch_batched(ti, tw, to, tk, too, 4096, args.seed, out_idx=oi, out_val=ov, stream=s)
+    s.synchronize()
+    breakdown = per_kernel_ms(gm.get_timing())
+    gm.set_option("timing", 0)
     gm.reset_options()
-    print(json.dumps({"workload": f"uneven batch: {nvec} vectors, Zipf(1.2) n+ on [10, 1e5] "
-                                  f"(nnz={int(off[-1])}), k from {{64,256,1024,4096}}, lognormal(0,2) weights",
-                      "ms_per_batch": ms, "registers_per_s": total / (ms / 1e3),
+    n = np.diff(off)
+    kern = uneven_kernel_rooflines(breakdown, n, kk)
+    dom = max((e for e in kern.values() if e["bound"] == "alu"), key=lambda e: e["kernel_ms"])
+    dom_k = {0: 256, 1: 1024, 2: 2048, 3: 4096}[int(dom["kernel"].split("class ")[1].rstrip("]")) % 4]
+    dom["probe_ceiling_arrivals_per_s"] = rate_ceiling(min(dom_k, 4096), args.seed)
+    dom["arrivals_per_s"] = dom["algorithmic_units"] / (dom["kernel_ms"] / 1e3)
+    dom["frac_of_probe"] = dom["arrivals_per_s"] / dom["probe_ceiling_arrivals_per_s"]
+    print(json.dumps({"metric": "Gumbel-Max registers/sec (FastGM form, uneven mixed-k batch)",
+                      "value": total / (ms / 1e3), "unit": "registers/s", "n_gpus": 1,
+                      "steps": max(2, args.steps // 4), "warmup": 1, "ms_per_step": ms,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"uneven batch: {nvec} vectors, Zipf(1.2) n+ on [10, 1e5] "
+                                             f"(nnz={int(off[-1])}), k from {{64,256,1024,4096}}, "
+                                             f"lognormal(0,2) weights, one captured graph"},
                       "vectors_per_s": nvec / (ms / 1e3), "entries_per_s": int(off[-1]) / (ms / 1e3),
+                      "roofline": dom, "kernels": kern, "kernels_ms_per_call": breakdown,
                       "autotuned": tuned, "graph": True, "input_gen_s": gen_s}), flush=True)
 
 
