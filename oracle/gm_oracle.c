@@ -352,6 +352,77 @@ static int32_t argmax_reg(int32_t k, const double *y)
     return jm;
 }
 
+/*
+ * The k registers of one sketch with what pruning needs to know about them:
+ * how many are still empty, and (once none is) which one holds the largest
+ * value y* = max_j y_j.  The largest register can only change when it is
+ * itself replaced, so its position is recomputed only then.
+ */
+typedef struct {
+    int32_t k;
+    int32_t *s;
+    double *y;
+    int32_t empty;
+    int32_t jstar;
+} regset_t;
+
+static void regset_init(regset_t *R, int32_t k, int32_t *s, double *y)
+{
+    R->k = k;
+    R->s = s;
+    R->y = y;
+    R->empty = k;
+    R->jstar = 0;
+    regs_empty(k, s, y);
+}
+
+/* y* once every register holds an arrival; +inf before (nothing prunes). */
+static double regset_ystar(const regset_t *R)
+{
+    return R->empty > 0 ? INFINITY : R->y[R->jstar];
+}
+
+/* Arrival (t, index) at server c: the register keeps the lexicographically
+ * smaller (key, index) pair. */
+static void regset_offer(regset_t *R, double t, int32_t index, int32_t c)
+{
+    if (R->s[c] < 0) {
+        R->y[c] = t;
+        R->s[c] = index;
+        if (--R->empty == 0)
+            R->jstar = argmax_reg(R->k, R->y);
+    } else if (lexless(t, index, R->y[c], R->s[c])) {
+        R->y[c] = t;
+        R->s[c] = index;
+        if (R->empty == 0 && c == R->jstar)
+            R->jstar = argmax_reg(R->k, R->y);
+    }
+}
+
+/*
+ * Emit queue q's arrivals until it has emitted `upto` of them (at most k),
+ * offering each to its server.  With `prune`, the queue closes at its first
+ * arrival later than y* (FastPrune, Sec. 2.2: its later arrivals are larger
+ * still, so none of them can replace a register; an arrival equal to y* is
+ * still offered).  Returns 1 when the queue is closed: pruned, or all of
+ * its k customers emitted.
+ */
+static int queue_release(queue_t *q, int32_t upto, int prune, regset_t *R, double *last,
+                         int64_t *arrivals)
+{
+    while (q->z < upto) {
+        double t;
+        int32_t c;
+        queue_next(q, R->k, &t, &c);
+        ++*arrivals;
+        *last = t;
+        if (prune && t > regset_ystar(R))
+            return 1;
+        regset_offer(R, t, q->index, c);
+    }
+    return q->z >= R->k;
+}
+
 static void scratch_grow_alg1(scratch_t *sc, int64_t n, int32_t k)
 {
     if (n <= sc->cap)
@@ -371,26 +442,35 @@ static void scratch_grow_alg1(scratch_t *sc, int64_t n, int32_t k)
     sc->alive = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
 }
 
+/* Release budget of queue i after a total budget R (Sec. 2.1): its share
+ * R v_i / S of the arrivals, rounded up, at most k. */
+static int32_t release_budget(double R, double v, double S, int32_t k)
+{
+    double Ri = ceil(R * (v / S));
+    return Ri >= (double)k ? k : (int32_t)Ri;
+}
+
 /*
- * Algorithm 1 (FastGM): FastSearch releases R_i = ceil(R v_i^*) arrivals of
- * every queue, R growing by Delta = k per round, until every server holds an
- * arrival; FastPrune then keeps releasing arrivals and closes a queue at its
- * first arrival later than y* = max_j y_j, recomputing the argmax j* when
- * the register holding it improves.
- * Readings applied where the pseudocode cannot run as printed:
- *  - R_i is capped at k (a queue has only k customers);
- *  - R_i is recomputed every round in FastPrune too, and a queue whose k
- *    customers are all released, or whose latest arrival already exceeds
- *    y*, is closed (as printed, a queue that has caught up with a stale R_i
- *    is never removed and the loop does not end);
- *  - an all-zero vector returns empty registers (FastSearch never ends);
+ * Algorithm 1 (FastGM, Sec. 2.2).  Every queue releases its share of a
+ * growing total budget (k more arrivals per round).  FastSearch: rounds run
+ * without pruning until every register holds an arrival.  FastPrune: the
+ * rounds go on, and a queue closes at its first arrival later than y*.
+ * Readings applied where the printed pseudocode cannot run as written:
+ *  - a queue's budget is capped at k (it has only k customers);
+ *  - the budget is recomputed in every FastPrune round, and a queue closes
+ *    once all of its k customers are out or its latest arrival already lies
+ *    above y* (with the budget of an earlier round, a queue that has caught
+ *    up would never be removed and the rounds would not end);
+ *  - a vector without positive weight returns empty registers (FastSearch
+ *    would never end);
  *  - "b_i < y_c" is the lexicographic (key, index) order; the prune test
- *    stays strict (an arrival equal to y* is still processed).
+ *    stays strict.
  */
 static int64_t vec_alg1(const int32_t *idx, const float *w, int64_t a, int64_t b,
                         int32_t k, uint64_t seed_mix, int32_t *s, double *y, scratch_t *sc)
 {
-    regs_empty(k, s, y);
+    regset_t R;
+    regset_init(&R, k, s, y);
     int64_t n = 0;
     for (int64_t e = a; e < b; ++e)
         if (w[e] > 0.0f)
@@ -414,127 +494,59 @@ static int64_t vec_alg1(const int32_t *idx, const float *w, int64_t a, int64_t b
         ++n;
     }
     int64_t arrivals = 0;
-    double R = 0.0;
-    int32_t kstar = k;
+    double budget = 0.0;
+    /* latest arrival of each queue (+0 before its first) */
+    double *last = (double *)calloc((size_t)n, sizeof(double));
     /* FastSearch */
-    while (kstar != 0) {
-        R += (double)k;
-        for (int64_t i = 0; i < n; ++i) {
-            queue_t *q = &sc->qs[i];
-            double Ri_d = ceil(R * (sc->ev[i] / S));
-            int32_t Ri = Ri_d >= (double)k ? k : (int32_t)Ri_d;
-            while (q->z < Ri) {
-                double t;
-                int32_t c;
-                queue_next(q, k, &t, &c);
-                ++arrivals;
-                if (s[c] < 0) {
-                    y[c] = t;
-                    s[c] = q->index;
-                    --kstar;
-                } else if (lexless(t, q->index, y[c], s[c])) {
-                    y[c] = t;
-                    s[c] = q->index;
-                }
-            }
-        }
+    while (R.empty > 0) {
+        budget += (double)k;
+        for (int64_t i = 0; i < n; ++i)
+            (void)queue_release(&sc->qs[i], release_budget(budget, sc->ev[i], S, k), 0, &R,
+                                &last[i], &arrivals);
     }
     /* FastPrune */
-    int32_t jstar = argmax_reg(k, y);
-    int64_t nalive = n;
+    int64_t nalive = 0;
     for (int64_t i = 0; i < n; ++i)
-        sc->alive[i] = i;
-    /* last emitted arrival time of each queue */
-    double *lastt = (double *)malloc(sizeof(double) * (size_t)n);
-    for (int64_t i = 0; i < n; ++i)
-        lastt[i] = sc->qs[i].O * sc->qs[i].r;
+        sc->alive[nalive++] = i;
     while (nalive > 0) {
-        R += (double)k;
+        budget += (double)k;
         int64_t keep = 0;
         for (int64_t m = 0; m < nalive; ++m) {
             int64_t i = sc->alive[m];
             queue_t *q = &sc->qs[i];
-            int closed = (q->z >= k) || (lastt[i] > y[jstar]);
-            double Ri_d = ceil(R * (sc->ev[i] / S));
-            int32_t Ri = Ri_d >= (double)k ? k : (int32_t)Ri_d;
-            while (!closed && q->z < Ri) {
-                double t;
-                int32_t c;
-                queue_next(q, k, &t, &c);
-                ++arrivals;
-                lastt[i] = t;
-                if (t > y[jstar]) {
-                    closed = 1;
-                    break;
-                }
-                if (lexless(t, q->index, y[c], s[c])) {
-                    y[c] = t;
-                    s[c] = q->index;
-                    if (c == jstar)
-                        jstar = argmax_reg(k, y);
-                }
-            }
-            if (q->z >= k)
-                closed = 1;
+            int closed = q->z >= k || last[i] > regset_ystar(&R);
+            if (!closed)
+                closed = queue_release(q, release_budget(budget, sc->ev[i], S, k), 1, &R,
+                                       &last[i], &arrivals);
             if (!closed)
                 sc->alive[keep++] = i;
         }
         nalive = keep;
     }
-    free(lastt);
+    free(last);
     return arrivals;
 }
 
 /*
- * Algorithm 2 (Stream-FastGM): each arriving element walks its arrivals in
- * ascending order; until every register is filled it only fills/updates,
- * afterwards it stops at its first arrival larger than y* (strict), and the
- * argmax j* is recomputed when the register holding it improves.  Reading:
- * the printed "if k == 0" tests the unreserved-server count k*.
+ * Algorithm 2 (Stream-FastGM, Sec. 3): the elements arrive one at a time;
+ * each emits its arrivals in ascending order, offering each to its server,
+ * and stops at its first arrival later than y* once every register holds an
+ * arrival (the prune of Sec. 2.2 against the registers as they stand).
+ * Reading: the printed "if k == 0" tests the count of registers still empty.
  */
 static int64_t vec_stream(const int32_t *idx, const float *w, int64_t a, int64_t b,
                           int32_t k, uint64_t seed_mix, int32_t *s, double *y, scratch_t *sc)
 {
-    regs_empty(k, s, y);
+    regset_t R;
+    regset_init(&R, k, s, y);
     int64_t arrivals = 0;
-    int32_t kstar = k;
-    int32_t jstar = 0;
-    int flag = 0;
     for (int64_t e = a; e < b; ++e) {
         if (!(w[e] > 0.0f))
             continue;
         queue_t q;
+        double last = 0.0;
         queue_start(&q, seed_mix, idx[e], w[e], sc->pi, sc->touched);
-        for (int32_t l = 1; l <= k; ++l) {
-            double t;
-            int32_t c;
-            queue_next(&q, k, &t, &c);
-            ++arrivals;
-            if (!flag) {
-                if (s[c] < 0) {
-                    y[c] = t;
-                    s[c] = idx[e];
-                    --kstar;
-                    if (kstar == 0) {
-                        flag = 1;
-                        jstar = argmax_reg(k, y);
-                    }
-                } else if (lexless(t, idx[e], y[c], s[c])) {
-                    y[c] = t;
-                    s[c] = idx[e];
-                }
-            }
-            if (flag) {
-                if (t > y[jstar])
-                    break;
-                if (lexless(t, idx[e], y[c], s[c])) {
-                    y[c] = t;
-                    s[c] = idx[e];
-                    if (c == jstar)
-                        jstar = argmax_reg(k, y);
-                }
-            }
-        }
+        (void)queue_release(&q, k, 1, &R, &last, &arrivals);
         queue_finish(&q);
     }
     return arrivals;
