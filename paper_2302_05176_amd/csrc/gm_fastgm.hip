@@ -260,14 +260,15 @@ __device__ __forceinline__ void reg_update(const VecCtx& c, int32_t srv, double 
   if (c.mode == kWalkNormal) contest_check(c, old, pk);
 }
 
-// max_j y_j as seen now (+inf while a register is empty).
+// max_j y_j as seen now (+inf while a register is empty).  The keys are
+// non-negative doubles or +inf, whose order is that of their bit patterns:
+// each lane takes a double maximum (one instruction per register), the wave
+// a bitwise one.
 __device__ __forceinline__ double wave_max_register(const VecCtx& c) {
-  unsigned long long m = 0;
-  for (int j = __lane_id(); j < c.k; j += kWave) {
-    const unsigned long long x = *reinterpret_cast<volatile lds_u64*>(&c.fullkey[j]);
-    m = x > m ? x : m;
-  }
-  return bitsd(wave_max_u64(m));
+  double m = 0.0;
+  for (int j = __lane_id(); j < c.k; j += kWave)
+    m = fmax(m, bitsd(*reinterpret_cast<volatile lds_u64*>(&c.fullkey[j])));
+  return bitsd(wave_max_u64(dbits(m)));
 }
 
 // ---------------------------------------------------------------------------
@@ -392,26 +393,63 @@ __device__ __forceinline__ void fy_step_flat(int32_t j, uint32_t& cval, uint32_t
 // * a lane's server is the displaced value of the last earlier lane with
 //   its target, else what it read at its target;
 // * a lane's write stands only if no later lane has its target.
-// One ballot per bit of the (1-based, at most GM_K_MAX) targets gives every
-// lane the lanes whose target equals its own target and those whose target
-// equals its position; the chains are followed by pointer jumping, at most
+// One ballot per bit of j - 1 (j the 1-based target, at most GM_K_MAX) gives
+// every lane the lanes whose target equals its own target and those whose
+// target equals its position; the chains are followed by pointer jumping, at most
 // six rounds for 64 lanes (none when no lane targets a position in its own
 // batch).  Lanes past the segment's stop carry negative targets and match
 // nothing.
-constexpr int kTargetBits = 13;
-static_assert(GM_K_MAX < (1 << kTargetBits), "targets must fit the ballot bits");
+// Bits of j - 1 compared for a segment width: its class bounds k by 256
+// (8 lanes), 1024 (16) or GM_K_MAX (64).
+template <int G>
+constexpr int target_bits() { return G == 8 ? 8 : (G == 16 ? 10 : 12); }
+static_assert(GM_K_MAX <= (1 << target_bits<64>()), "targets - 1 must fit the ballot bits");
 
-__device__ __forceinline__ bool fy_resolve64(int32_t j, int32_t z, uint32_t& cval, uint32_t& disp) {
+// `inwin` false: no lane targets a position of its own batch, so no lane's
+// displaced value changes during the batch (the chains are empty).
+template <int G>
+__device__ __forceinline__ bool fy_resolve(int32_t j, int32_t z, bool inwin, uint32_t& cval,
+                                           uint32_t& disp) {
+  constexpr int kBits = target_bits<G>();
   const uint32_t lane = __lane_id();
-  const uint64_t valid = __ballot(j >= 0);
-  uint64_t same = valid, at_z = valid;
+  // this lane's segment
+  const uint64_t seg =
+      G == 64 ? ~0ull : (((1ull << G) - 1ull) << (lane & ~static_cast<uint32_t>(G - 1)));
+  const uint64_t valid = __ballot(j >= 0) & seg;
+  // The sets are built as complements, per 32-bit half: a lane leaves a set
+  // at the first bit of j - 1 where it differs (a lane outside the segment,
+  // or invalid, is out from the start).  `m ^ -bit` is zero where a lane
+  // agrees with this lane's bit, so each bit costs an xor and an or per
+  // half, with the ballot as a scalar operand.
+  uint32_t ns_lo = ~static_cast<uint32_t>(valid), ns_hi = ~static_cast<uint32_t>(valid >> 32);
+  uint32_t nz_lo = ns_lo, nz_hi = ns_hi;
+  const uint32_t jm = static_cast<uint32_t>(j) - 1u, zm = static_cast<uint32_t>(z) - 1u;
+  if (inwin) {
 #pragma unroll
-  for (int b = 0; b < kTargetBits; ++b) {
-    const uint64_t m = __ballot(((j >> b) & 1) != 0);
-    same &= ((j >> b) & 1) ? m : ~m;
-    at_z &= ((z >> b) & 1) ? m : ~m;
+    for (int b = 0; b < kBits; ++b) {
+      const uint64_t m = __ballot(((jm >> b) & 1u) != 0);
+      const uint32_t mlo = static_cast<uint32_t>(m), mhi = static_cast<uint32_t>(m >> 32);
+      const uint32_t jb = 0u - ((jm >> b) & 1u);
+      const uint32_t zb = 0u - ((zm >> b) & 1u);
+      ns_lo |= mlo ^ jb;
+      ns_hi |= mhi ^ jb;
+      nz_lo |= mlo ^ zb;
+      nz_hi |= mhi ^ zb;
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < kBits; ++b) {
+      const uint64_t m = __ballot(((jm >> b) & 1u) != 0);
+      const uint32_t jb = 0u - ((jm >> b) & 1u);
+      ns_lo |= static_cast<uint32_t>(m) ^ jb;
+      ns_hi |= static_cast<uint32_t>(m >> 32) ^ jb;
+    }
+    nz_lo = nz_hi = ~0u;
   }
-  if (j < 0) same = 0;
+  // (a lane past the stop, j < 0, neither swaps nor reads: its sets are
+  // empty; its position may exceed k, past the bits compared)
+  const uint64_t same = j < 0 ? 0ull : ~((static_cast<uint64_t>(ns_hi) << 32) | ns_lo);
+  const uint64_t at_z = j < 0 ? 0ull : ~((static_cast<uint64_t>(nz_hi) << 32) | nz_lo);
   const uint64_t below = (1ull << lane) - 1ull;
   // displaced values along the chains of earlier lanes targeting z
   const uint64_t zsrc = at_z & below;
@@ -442,10 +480,10 @@ template <int G, int... Ls>
 __device__ __forceinline__ bool fy_batch(std::integer_sequence<int, Ls...>, int32_t j, int32_t z,
                                          bool inwin, uint32_t& cval, uint32_t& disp) {
   // (64-lane segments only: for 8 and 16 lanes the sweep is a few row
-  // broadcasts, and the ballots' registers spill there)
+  // broadcasts; resolved by ballots as well, they spilled 107 VGPRs and ran
+  // 3% slower at k = 256 and 1024)
   if constexpr (G == 64) {
-    (void)inwin;
-    return fy_resolve64(j, z, cval, disp);
+    return fy_resolve<G>(j, z, inwin, cval, disp);
   } else {
     uint64_t after = ~seg_first_lanes<G>(), before = 0, killm = 0;
     // computed step by step with two scalar operations each: folded to
@@ -1455,14 +1493,21 @@ __device__ __forceinline__ void class_body(const FastArgs& fa) {
   }
 }
 
+// Waves per SIMD the register allocation aims for: three (168 VGPRs) where
+// the LDS lets three waves per SIMD in; the 64-lane-segment classes
+// (k > 1024) hold one workgroup of eight waves per CU by their LDS, so two
+// waves per SIMD, and may use the 256 VGPRs that leaves without spilling.
+template <int G>
+constexpr int class_waves_per_eu() { return G == 64 ? 2 : 3; }
+
 template <int W, int G>
-__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(class_waves_per_eu<G>())))
 void fastgm_class_kernel(FastArgs fa) {
   class_body<W, G, false>(fa);
 }
 
 template <int W, int G>
-__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(class_waves_per_eu<G>())))
 void fastgm_big_kernel(FastArgs fa) {
   class_body<W, G, true>(fa);
 }
@@ -1640,27 +1685,20 @@ __global__ __launch_bounds__(kBigBlock) void big_sum_kernel(FastArgs fa) {
     if (tid == 0) sbad = 0;
     double part = 0.0;
     bool badl = false;
-    // sixteen independent loads per lane in flight per step
-    constexpr int kU = 16;
-    int64_t e = e0 + tid;
-    for (; e + (kU - 1) * kBigBlock < e1; e += kU * kBigBlock) {
-      float wv[kU];
+    // a chunk's weights in one round: every lane's loads in flight together
+    constexpr int kU = static_cast<int>(kBigChunk / kBigBlock);
+    float wv[kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) wv[u] = p.w[e + u * kBigBlock];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        if (!weight_valid(wv[u]))
-          badl = true;
-        else
-          part += static_cast<double>(wv[u]);
-      }
+    for (int u = 0; u < kU; ++u) {
+      const int64_t e = e0 + u * kBigBlock + tid;
+      wv[u] = e < e1 ? p.w[e] : 0.0f;
     }
-    for (; e < e1; e += kBigBlock) {
-      const float wv = p.w[e];
-      if (!weight_valid(wv))
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (!weight_valid(wv[u]))
         badl = true;
       else
-        part += static_cast<double>(wv);
+        part += static_cast<double>(wv[u]);
     }
     __syncthreads();
     if (badl) sbad = 1;
@@ -1746,17 +1784,22 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
     if (tid == 0) scount = 0;
     __syncthreads();
     bool badl = false;
-    // four entries per lane per step, their loads issued together
+    // four entries per lane per step, their loads issued together one step
+    // ahead, so that a step's arithmetic hides the next step's loads
     constexpr int kPU = 4;
-    for (int64_t eb = e0; eb < e1; eb += kPU * kBigBlock) {
-      float wv[kPU];
-      int32_t iv[kPU];
+    float wv[kPU], wn[kPU];
+    int32_t iv[kPU], inx[kPU];
+    auto load_step = [&](int64_t eb, float (&wd)[kPU], int32_t (&id)[kPU]) {
 #pragma unroll
       for (int u = 0; u < kPU; ++u) {
         const int64_t e = eb + u * kBigBlock + tid;
-        wv[u] = e < e1 ? p.w[e] : 0.0f;
-        iv[u] = e < e1 ? p.idx[e] : 0;
+        wd[u] = e < e1 ? p.w[e] : 0.0f;
+        id[u] = e < e1 ? p.idx[e] : 0;
       }
+    };
+    load_step(e0, wv, iv);
+    for (int64_t eb = e0; eb < e1; eb += kPU * kBigBlock) {
+      load_step(eb + kPU * kBigBlock, wn, inx);
 #pragma unroll
       for (int u = 0; u < kPU; ++u) {
         const int64_t e = eb + u * kBigBlock + tid;
@@ -1780,6 +1823,11 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
           // (at most kBigChunk candidates per chunk: the list always has room)
           if (cand) slist[base + __popcll(m & lanemask_lt())] = static_cast<int32_t>(e - d.a);
         }
+      }
+#pragma unroll
+      for (int u = 0; u < kPU; ++u) {
+        wv[u] = wn[u];
+        iv[u] = inx[u];
       }
     }
     // a negative index poisons the vector (the walk reads the flag; this
@@ -2021,7 +2069,7 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   tid = timing_begin("big_sum_kernel", false, stream, &ta);
-  hipLaunchKernelGGL(big_sum_kernel, dim3(cus * 4), dim3(kBigBlock), 0, stream, fa);
+  hipLaunchKernelGGL(big_sum_kernel, dim3(cus * 8), dim3(kBigBlock), 0, stream, fa);
   timing_end(tid, ta, stream);
   tid = timing_begin("big_probe_kernel", false, stream, &ta);
   hipLaunchKernelGGL(big_probe_kernel, dim3(cus * 8), dim3(kBigBlock), 0, stream, fa);
