@@ -331,6 +331,12 @@ gm_status gm_reset_data_errors(hipStream_t stream);
  *   GM_OPT_SMALL_WAVES   [0] waves per workgroup of the kernels for vectors
  *                        of up to 32768 entries (0: chosen from k; else
  *                        1, 2, 4 or 8).
+ *   GM_OPT_WAVE_LIM      [8191] registers-per-block tiling of the k <= 256
+ *                        kernel: vectors of at most this many entries are
+ *                        sketched one per wave, each wave with a register
+ *                        set of its own; larger ones by the whole workgroup
+ *                        sharing one set.  0 (one set per workgroup for
+ *                        every vector) or 2^m - 1 for m = 4..15.
  *   GM_OPT_TIMING        [0] 1 brackets every launch of a sketch call with
  *                        HIP events on its stream (read with gm_get_timing);
  *                        2 only the sketch kernels themselves (FastGM class
@@ -339,7 +345,10 @@ gm_status gm_reset_data_errors(hipStream_t stream);
  *   GM_OPT_STATS         [0] 1 makes FastGM calls accumulate work counters
  *                        (read them with gm_get_stats); costs a few atomics
  *                        per vector.
- * Returns GM_ERR_INVALID_ARG for an unknown option or out-of-range value.
+ * Options are process-wide and read once per call (atomics): a change made
+ * by another host thread, gm_autotune's included, applies from some later
+ * call on.  Returns GM_ERR_INVALID_ARG for an unknown option or out-of-range
+ * value.
  */
 typedef enum {
     GM_OPT_POS_BITS = 0,
@@ -349,7 +358,8 @@ typedef enum {
     GM_OPT_STATS = 4,
     GM_OPT_SEG_REST = 5,
     GM_OPT_SMALL_WAVES = 6,
-    GM_OPT_TIMING = 7
+    GM_OPT_TIMING = 7,
+    GM_OPT_WAVE_LIM = 8
 } gm_option;
 gm_status gm_set_option(gm_option opt, int64_t value);
 
@@ -380,7 +390,8 @@ void gm_reset_timing(void);
 
 /*
  * gm_autotune -- pick the FastGM schedule options (GM_OPT_SMALL_WAVES,
- * GM_OPT_SEG_REST, GM_OPT_MAP_LOAD, GM_OPT_REPUBLISH) for a batch like this
+ * GM_OPT_SEG_REST, GM_OPT_MAP_LOAD, GM_OPT_REPUBLISH and the
+ * registers-per-block tiling GM_OPT_WAVE_LIM) for a batch like this
  * one by timing it: coordinate descent over each option's grid, median of
  * `reps` timed runs per point (HIP events on `stream`), then the best
  * setting is applied process-wide.  Arguments as gm_sketch (k_per_vec and
@@ -395,6 +406,7 @@ typedef struct {
     int32_t small_waves, map_load, seg_rest, republish;
     double ms;          /* median time of the chosen setting */
     int32_t from_cache; /* 1 if taken from the cache without timing */
+    int32_t wave_lim;   /* GM_OPT_WAVE_LIM chosen */
 } gm_tune_result;
 gm_status gm_autotune(const int32_t *indices, const float *weights, const int64_t *offsets,
                       int64_t nvec, const int32_t *k_per_vec, const int64_t *out_offsets,

@@ -22,7 +22,7 @@ GM_FORM_PLAIN = 1
 GM_K_MAX = 4096
 
 OPTIONS = {"pos_bits": 0, "t0_scale_ppm": 1, "map_load": 2, "republish": 3, "stats": 4,
-           "seg_rest": 5, "small_waves": 6, "timing": 7}
+           "seg_rest": 5, "small_waves": 6, "timing": 7, "wave_lim": 8}
 STATS = ["vectors", "iterations", "arrivals", "kept", "elements", "heavy", "heavy_batches",
          "passes", "resolves", "cyc_prep", "cyc_walk", "cyc_seg", "cyc_extra", "cyc_out"]
 
@@ -32,7 +32,8 @@ _lib = None
 class TuneResult(ctypes.Structure):
     _fields_ = [("small_waves", ctypes.c_int32), ("map_load", ctypes.c_int32),
                 ("seg_rest", ctypes.c_int32), ("republish", ctypes.c_int32),
-                ("ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
+                ("ms", ctypes.c_double), ("from_cache", ctypes.c_int32),
+                ("wave_lim", ctypes.c_int32)]
 
 
 class GMError(RuntimeError):

@@ -16,7 +16,7 @@ hipError_t launch_plain(const SketchArgs& p, const PlainScratch& ps, int cus, hi
 int64_t plain_scratch_regs(int cus);
 int64_t plain_scratch_counters(int cus);
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
-                         int republish, double seg_rest, int small_waves, int32_t* list,
+                         int republish, double seg_rest, int small_waves, int wave_lim, int32_t* list,
                          void* plan, void* big, int32_t* pool, int64_t pool_cap,
                          void* heavy, int64_t heavy_waves, void* part, int update, int cus,
                          unsigned long long* stats, hipStream_t stream);
@@ -114,6 +114,7 @@ std::atomic<int> g_map_load{14};
 std::atomic<int> g_republish{8};
 std::atomic<double> g_seg_rest{12.0};
 std::atomic<int> g_small_waves{0};
+std::atomic<int> g_wave_lim{8191};
 std::atomic<bool> g_stats{false};
 
 gm_status from_hip(hipError_t e) {
@@ -273,7 +274,7 @@ gm_status sketch_common(const int32_t* indices, const float* weights, const int6
   s = plan_workspace(st, stream, nvec, &ws);
   if (s != GM_OK) return s;
   return from_hip(gm::launch_fastgm(a, g_pos_bits, g_t0_scale, g_map_load, g_republish,
-                                    g_seg_rest, g_small_waves, ws->list, ws->plan, ws->big,
+                                    g_seg_rest, g_small_waves, g_wave_lim, ws->list, ws->plan, ws->big,
                                     ws->pool, kPoolCap, ws->heavy, ws->heavy_waves, ws->part, update,
                                     st->cus, g_stats ? st->stats : nullptr, stream));
 }
@@ -454,6 +455,11 @@ gm_status gm_set_option(gm_option opt, int64_t value) {
         std::lock_guard<std::mutex> lock(g_mu);
         gm::timing_enable(static_cast<int>(value));
       }
+      return GM_OK;
+    case GM_OPT_WAVE_LIM:
+      if (value != 0 && (value < 15 || value > 32767 || ((value + 1) & value) != 0))
+        return GM_ERR_INVALID_ARG;
+      g_wave_lim = static_cast<int>(value);
       return GM_OK;
     case GM_OPT_STATS:
       if (value != 0 && value != 1) return GM_ERR_INVALID_ARG;

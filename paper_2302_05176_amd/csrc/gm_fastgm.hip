@@ -1845,18 +1845,18 @@ __global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
   }
 }
 
-// Vectors of at most this many entries are sketched one per wave when the
-// register arrays are small enough for a set per wave (k <= 256); a power of
-// two minus one, so that it falls between the planner's log2 size bins.
-constexpr int64_t kWaveLim = 2047;
-
 // Waves per workgroup of a class (four, eight for k > 2048 and for big
 // vectors; halved while the LDS does not fit in 160 KB), and its one-wave
-// size limit.
-void class_shape(int sc, int k_max, int small_waves, int* waves, int64_t* wave_lim) {
+// size limit: vectors of at most `one_wave` entries are sketched one per
+// wave where the register arrays are small enough for a set per wave
+// (k <= 256).  The limit is a power of two minus one, so that it falls
+// between the planner's log2 size bins; 8191 by default (document batch at
+// k = 256: 0 -> 0.648 ms, 511 -> 0.599, 2047 -> 0.535, 8191 -> 0.527,
+// 32767 -> 0.528).
+void class_shape(int sc, int k_max, int small_waves, int one_wave, int* waves, int64_t* wave_lim) {
   int want = sc == 0 ? (k_max > 2048 ? 8 : 4) : 8;
   if (sc == 0 && small_waves > 0) want = small_waves;
-  const int64_t lim = (sc == 0 && k_max <= 256) ? kWaveLim : 0;
+  const int64_t lim = (sc == 0 && k_max <= 256) ? one_wave : 0;
   int w = want;
   while (w > 1 && fastgm_lds_bytes(k_max, w, lim > 0 ? w : 1) + w * sizeof(FgShared) > 160 * 1024)
     w /= 2;
@@ -2039,7 +2039,7 @@ static hipError_t launch_class_w(const FastArgs& fa, int waves, int cus, hipStre
 constexpr int64_t kLimM = 32768;
 
 hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int map_load,
-                         int republish, double seg_rest, int small_waves, int32_t* list,
+                         int republish, double seg_rest, int small_waves, int one_wave, int32_t* list,
                          void* plan, void* big, int32_t* pool, int64_t pool_cap,
                          void* heavy, int64_t heavy_waves, void* part, int update, int cus,
                          unsigned long long* stats, hipStream_t stream) {
@@ -2087,7 +2087,7 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
       fa.cls = sc * kKClasses + kc;
       fa.lds_k = s.k_max < kclass_hi(kc) ? s.k_max : kclass_hi(kc);
       int waves = 1;
-      class_shape(sc, fa.lds_k, small_waves, &waves, &fa.wave_lim);
+      class_shape(sc, fa.lds_k, small_waves, one_wave, &waves, &fa.wave_lim);
       const int g = segment_lanes(fa.lds_k);
       e = g == 8 ? launch_class_w<8>(fa, waves, cus, stream)
                  : (g == 16 ? launch_class_w<16>(fa, waves, cus, stream)

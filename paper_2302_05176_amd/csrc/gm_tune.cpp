@@ -1,10 +1,12 @@
 // gm_tune.cpp -- autotuner for the FastGM launch options.
 //
 // The FastGM kernels expose a few schedule knobs that change the work split
-// but never the result: waves sharing one small vector, the per-lane table
-// load before an element moves to the 16-lane segment path, the expected
-// walk length that sends an element there directly from its first arrival,
-// and the threshold republish period.  gm_autotune times the caller's own
+// but never the result: waves sharing one small vector, the registers-per-
+// block tiling (up to which size a vector is sketched by one wave with its
+// own register set rather than by a workgroup sharing one), the per-lane
+// table load before an element moves to the segment path, the expected walk
+// length that sends an element there directly from its first arrival, and
+// the threshold republish period.  gm_autotune times the caller's own
 // batch under a coordinate descent over those knobs (HIP events on the
 // caller's stream, median of `reps` runs per point), keeps the fastest
 // setting, and records it in a JSON-lines cache keyed by (GPU architecture,
@@ -31,7 +33,7 @@ namespace {
 std::mutex g_tune_mu;
 
 struct Knobs {
-  int64_t small_waves, map_load, seg_rest, republish;
+  int64_t small_waves, map_load, seg_rest, republish, wave_lim;
 };
 
 gm_status set_knobs(const Knobs& k) {
@@ -39,6 +41,7 @@ gm_status set_knobs(const Knobs& k) {
   if ((s = gm_set_option(GM_OPT_SMALL_WAVES, k.small_waves)) != GM_OK) return s;
   if ((s = gm_set_option(GM_OPT_MAP_LOAD, k.map_load)) != GM_OK) return s;
   if ((s = gm_set_option(GM_OPT_SEG_REST, k.seg_rest)) != GM_OK) return s;
+  if ((s = gm_set_option(GM_OPT_WAVE_LIM, k.wave_lim)) != GM_OK) return s;
   return gm_set_option(GM_OPT_REPUBLISH, k.republish);
 }
 
@@ -73,7 +76,8 @@ std::string cache_key(int32_t k_max, int64_t nvec, int64_t nnz, bool batched) {
 }
 
 // Very small reader for the lines this file writes:
-// {"key": "...", "small_waves": a, "map_load": b, "seg_rest": c, "republish": d, "ms": e}
+// {"key": "...", "small_waves": a, "map_load": b, "seg_rest": c, "republish": d,
+//  "wave_lim": f, "ms": e}  (a line without wave_lim has the default 8191)
 bool parse_line(const std::string& line, std::string& key, Knobs& k, double& ms) {
   auto field = [&](const char* name, std::string& out) {
     const std::string pat = std::string("\"") + name + "\":";
@@ -100,6 +104,8 @@ bool parse_line(const std::string& line, std::string& key, Knobs& k, double& ms)
   k.map_load = std::atoll(b.c_str());
   k.seg_rest = std::atoll(c.c_str());
   k.republish = std::atoll(d.c_str());
+  std::string f;
+  k.wave_lim = field("wave_lim", f) ? std::atoll(f.c_str()) : 8191;
   ms = std::atof(e.c_str());
   return true;
 }
@@ -128,7 +134,8 @@ void cache_store(const std::string& key, const Knobs& k, double ms) {
   if (!out) return;
   out << "{\"key\": \"" << key << "\", \"small_waves\": " << k.small_waves
       << ", \"map_load\": " << k.map_load << ", \"seg_rest\": " << k.seg_rest
-      << ", \"republish\": " << k.republish << ", \"ms\": " << ms << "}\n";
+      << ", \"republish\": " << k.republish << ", \"wave_lim\": " << k.wave_lim
+      << ", \"ms\": " << ms << "}\n";
 }
 
 }  // namespace
@@ -149,7 +156,7 @@ extern "C" gm_status gm_autotune(const int32_t* indices, const float* weights,
   if (e == hipSuccess) e = hipMemcpy(&ends[1], offsets + nvec, sizeof(int64_t), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return GM_ERR_DEVICE;
   const std::string key = cache_key(k_max, nvec, ends[1] - ends[0], batched);
-  Knobs best{0, 14, 12, 8};
+  Knobs best{0, 14, 12, 8, 8191};
   double best_ms = 0.0;
   if (use_cache && cache_lookup(key, best, best_ms)) {
     gm_status s = set_knobs(best);
@@ -159,6 +166,7 @@ extern "C" gm_status gm_autotune(const int32_t* indices, const float* weights,
       result->map_load = static_cast<int32_t>(best.map_load);
       result->seg_rest = static_cast<int32_t>(best.seg_rest);
       result->republish = static_cast<int32_t>(best.republish);
+      result->wave_lim = static_cast<int32_t>(best.wave_lim);
       result->ms = best_ms;
       result->from_cache = 1;
     }
@@ -199,15 +207,24 @@ extern "C" gm_status gm_autotune(const int32_t* indices, const float* weights,
   const std::vector<int64_t> grid_seg = {4, 8, 12, 16, 32, 64};
   const std::vector<int64_t> grid_map = {8, 10, 12, 14, 16};
   const std::vector<int64_t> grid_rep = {4, 8, 16};
-  for (int axis = 0; axis < 4 && s == GM_OK; ++axis) {
-    const std::vector<int64_t>& grid =
-        axis == 0 ? grid_waves : axis == 1 ? grid_seg : axis == 2 ? grid_map : grid_rep;
+  // registers-per-block tiling: only the k <= 256 kernel has a choice (a
+  // batch with per-vector k may have such vectors whatever its k_max)
+  const std::vector<int64_t> grid_lim = (k_max <= 256 || batched)
+                                            ? std::vector<int64_t>{0, 511, 2047, 8191, 32767}
+                                            : std::vector<int64_t>{};
+  for (int axis = 0; axis < 5 && s == GM_OK; ++axis) {
+    const std::vector<int64_t>& grid = axis == 0   ? grid_waves
+                                       : axis == 1 ? grid_seg
+                                       : axis == 2 ? grid_map
+                                       : axis == 3 ? grid_rep
+                                                   : grid_lim;
     for (int64_t v : grid) {
       Knobs k = best;
-      int64_t* field = axis == 0 ? &k.small_waves
+      int64_t* field = axis == 0   ? &k.small_waves
                        : axis == 1 ? &k.seg_rest
                        : axis == 2 ? &k.map_load
-                                   : &k.republish;
+                       : axis == 3 ? &k.republish
+                                   : &k.wave_lim;
       if (*field == v) continue;
       *field = v;
       double ms = 0.0;
@@ -230,6 +247,7 @@ extern "C" gm_status gm_autotune(const int32_t* indices, const float* weights,
     result->map_load = static_cast<int32_t>(best.map_load);
     result->seg_rest = static_cast<int32_t>(best.seg_rest);
     result->republish = static_cast<int32_t>(best.republish);
+    result->wave_lim = static_cast<int32_t>(best.wave_lim);
     result->ms = best_ms;
     result->from_cache = 0;
   }

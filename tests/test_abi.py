@@ -98,6 +98,11 @@ def test_options_validation(lib):
     assert lib.gm_set_option(7, -1) == N.GM_ERR_INVALID_ARG
     for level in (2, 1, 0):
         assert lib.gm_set_option(7, level) == N.GM_OK
+    # registers-per-block tiling: 0 or 2^m - 1, m = 4..15
+    for bad in (7, 100, 2048, 65535, -1):
+        assert lib.gm_set_option(8, bad) == N.GM_ERR_INVALID_ARG
+    for good in (0, 15, 511, 8191, 32767, 2047):
+        assert lib.gm_set_option(8, good) == N.GM_OK
     assert lib.gm_status_string(1) == b"invalid argument"
 
 

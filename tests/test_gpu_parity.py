@@ -93,7 +93,8 @@ def test_document_batch_k256(gm):
                                      ("map_load", 2), ("map_load", 16), ("t0_scale_ppm", 1),
                                      ("t0_scale_ppm", 100_000), ("republish", 1),
                                      ("republish", 64), ("seg_rest", 0),
-                                     ("seg_rest", 1000000)])
+                                     ("seg_rest", 1000000), ("wave_lim", 0),
+                                     ("wave_lim", 15), ("wave_lim", 32767)])
 def test_forced_internal_paths(gm, opt, val):
     """Debug knobs force packed-prefix contests (exact re-resolution), the
     wave-cooperative heavy path, the enlarge-and-repeat fallback and other
@@ -429,7 +430,8 @@ def test_autotune_keeps_results_and_caches(gm, tmp_path, monkeypatch):
         assert r1["from_cache"] == 0 and r1["ms"] > 0
         r2 = gm.autotune(t(idx), t(w), t(off), 128, 3, reps=1)
         assert r2["from_cache"] == 1
-        assert (r2["small_waves"], r2["seg_rest"]) == (r1["small_waves"], r1["seg_rest"])
+        assert (r2["small_waves"], r2["seg_rest"], r2["wave_lim"]) == \
+            (r1["small_waves"], r1["seg_rest"], r1["wave_lim"])
         _assert_same(_gpu_sketch(gm, idx, w, off, 128, 3),
                      oracle.sketch(idx, w, off, 128, 3, form=oracle.FORM_STREAM), "tuned")
     finally:
