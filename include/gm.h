@@ -311,9 +311,10 @@ gm_status gm_reset_data_errors(hipStream_t stream);
  * gm_set_option -- process-wide tuning and testing knobs (defaults in
  * brackets).  They change how much work is done or which internal path runs,
  * never the result:
- *   GM_OPT_POS_BITS      [24] entry-position bits in a packed FastGM register,
- *                        8..62; more bits means fewer key bits and more
- *                        exact re-resolutions of tied prefixes.
+ *   GM_OPT_POS_BITS      [31] element-index bits in a packed FastGM register
+ *                        (the index sits below the key's top bits), 31..62;
+ *                        more bits means fewer key bits and more exact
+ *                        re-resolutions of tied prefixes.
  *   GM_OPT_T0_SCALE_PPM  [1000000] scale of the closed-form pruning threshold
  *                        in parts per million; small values force the
  *                        enlarge-and-repeat fallback.

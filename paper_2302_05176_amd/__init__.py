@@ -351,7 +351,7 @@ def reset_stats(stream=None) -> None:
 
 
 def reset_options() -> None:
-    for name, v in (("pos_bits", 24), ("t0_scale_ppm", 1_000_000), ("map_load", 14),
+    for name, v in (("pos_bits", 31), ("t0_scale_ppm", 1_000_000), ("map_load", 14),
                     ("republish", 8), ("stats", 0), ("seg_rest", 12),
                     ("small_waves", 0), ("timing", 0), ("wave_lim", 8191)):
         set_option(name, v)

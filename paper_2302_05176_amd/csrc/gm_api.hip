@@ -108,7 +108,7 @@ DeviceState g_dev[kMaxDevices];
 // beside a serving loop, say) takes effect from some call on and never
 // tears a value; a call sees a mix of old and new options only while a
 // change is under way.
-std::atomic<int> g_pos_bits{24};
+std::atomic<int> g_pos_bits{31};
 std::atomic<double> g_t0_scale{1.0};
 std::atomic<int> g_map_load{14};
 std::atomic<int> g_republish{8};
@@ -429,7 +429,8 @@ gm_status gm_reset_data_errors(hipStream_t stream) {
 gm_status gm_set_option(gm_option opt, int64_t value) {
   switch (opt) {
     case GM_OPT_POS_BITS:
-      if (value < 8 || value > 62) return GM_ERR_INVALID_ARG;
+      // the packed word's low bits hold a non-negative int32 index
+      if (value < 31 || value > 62) return GM_ERR_INVALID_ARG;
       g_pos_bits = static_cast<int>(value);
       return GM_OK;
     case GM_OPT_T0_SCALE_PPM:

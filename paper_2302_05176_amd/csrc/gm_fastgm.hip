@@ -17,7 +17,8 @@
 // fewer than 2048 entries are handled by one wave each:
 //  * Registers live in LDS.  A register is two 64-bit words: `packed` holds
 //    the top bits of the key (positive doubles order like their bit patterns)
-//    above a pos_bits-wide entry position, updated by 64-bit LDS atomic-min;
+//    above the element index (31 bits by default), updated by 64-bit LDS
+//    atomic-min;
 //    `fullkey` holds the exact key bits, atomic-min'ed by every arrival that
 //    lowers or ties the packed prefix.  Two different entries whose keys share
 //    the packed prefix raise a per-vector "contest" flag, and the vector's
@@ -97,7 +98,7 @@ struct HeavyRec {
   uint64_t P;      // hash prefix
   double r;        // 1 / v
   double O;        // O_z
-  int32_t pos;     // entry position in the vector
+  int32_t unused;  // (keeps the fields' dwords)
   int32_t ind;     // element index
   int32_t z;       // steps done
   int32_t nent;
@@ -158,7 +159,7 @@ struct BigInfo {
 
 struct FastArgs {
   SketchArgs s;
-  int32_t pos_bits;   // entry-position bits in a packed register
+  int32_t pos_bits;   // element-index bits in a packed register (31..62)
   double t0_scale;    // multiplies the closed-form threshold (1.0)
   int32_t map_load;   // table entries per lane before the element goes to the wave path
   int32_t republish;  // light iterations between threshold republishes (power of two)
@@ -224,13 +225,15 @@ __device__ __forceinline__ void stat_add(unsigned long long* stats, int which,
   if (stats && v) atomicAdd(&stats[which], v);
 }
 
-__device__ __forceinline__ unsigned long long packed_key(const VecCtx& c, double t, uint32_t pos) {
+// Packed register word of arrival (t, index): the key's top 64 - B bits
+// above the index.  (The index itself, not the entry's position, so that
+// the writeback needs no gather, and duplicate indices never contest.)
+__device__ __forceinline__ unsigned long long packed_key(const VecCtx& c, double t, int32_t ind) {
   const int B = c.pos_bits;
-  const unsigned long long mask = (1ull << B) - 1ull;
-  return ((dbits(t) >> (B - 1)) << B) | (pos & mask);
+  return ((dbits(t) >> (B - 1)) << B) | static_cast<uint32_t>(ind);
 }
 
-// Offer arrival (t, entry pos, index ind) to register srv.  Normal mode
+// Offer arrival (t, index ind) to register srv.  Normal mode
 // returns the packed word the register held before (check it later with
 // contest_check); the exact-key minimum needs no answer.
 __device__ __forceinline__ unsigned long long reg_offer(const VecCtx& c, int32_t srv, double t,
@@ -253,9 +256,8 @@ __device__ __forceinline__ void contest_check(const VecCtx& c, unsigned long lon
   if ((old >> B) == (pk >> B) && old != pk) *c.contest = 1;
 }
 
-__device__ __forceinline__ void reg_update(const VecCtx& c, int32_t srv, double t, uint32_t pos,
-                                           int32_t ind) {
-  const unsigned long long pk = packed_key(c, t, pos);
+__device__ __forceinline__ void reg_update(const VecCtx& c, int32_t srv, double t, int32_t ind) {
+  const unsigned long long pk = packed_key(c, t, ind);
   const unsigned long long old = reg_offer(c, srv, t, pk, ind);
   if (c.mode == kWalkNormal) contest_check(c, old, pk);
 }
@@ -546,7 +548,6 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, const lds_i
   __threadfence_block();
   const int k = c.k;
   bool active = false;
-  uint32_t hpos = 0;
   int32_t ind = 0;
   double r = 0.0, O = 0.0;
   uint64_t P = 0;
@@ -589,7 +590,6 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, const lds_i
         P = (static_cast<uint64_t>(rec_field<G, 1>(rec)) << 32) | rec_field<G, 0>(rec);
         r = bitsd((static_cast<uint64_t>(rec_field<G, 3>(rec)) << 32) | rec_field<G, 2>(rec));
         O = bitsd((static_cast<uint64_t>(rec_field<G, 5>(rec)) << 32) | rec_field<G, 4>(rec));
-        hpos = rec_field<G, 6>(rec);
         ind = static_cast<int32_t>(rec_field<G, 7>(rec));
         z0 = static_cast<int>(rec_field<G, 8>(rec)) + 1;
         const int nent = static_cast<int>(rec_field<G, 9>(rec));
@@ -658,7 +658,7 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, const lds_i
         fy_batch<G>(std::make_integer_sequence<int, G>{}, jf, z, inwin, cval, disp);
     if (li < f && !killed) pm[j] = static_cast<uint16_t>((hgen << 13) | disp);
     if (li < f) {
-      pend_pk = packed_key(c, t, hpos);
+      pend_pk = packed_key(c, t, ind);
       pend_old = reg_offer(c, static_cast<int32_t>(cval) - 1, t, pend_pk, ind);
       pend = c.mode == kWalkNormal;
     }
@@ -746,12 +746,11 @@ struct Queue {
   lds_u64* P;
   lds_f64* r;
   lds_f64* O;
-  lds_u32* pos;
   lds_i32* ind;
   lds_u32* j1;
 };
 
-__host__ __device__ constexpr size_t queue_bytes() { return kQueueCap * (8 + 8 + 8 + 4 + 4 + 4); }
+__host__ __device__ constexpr size_t queue_bytes() { return kQueueCap * (8 + 8 + 8 + 4 + 4); }
 
 // One wave's share of a walk over the vector's entries.  Each iteration:
 //  (a) while the queue has room, a uniform probe pass takes the next 64
@@ -776,7 +775,6 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
   const int lane = __lane_id();
   const double c1 = 1.0 / static_cast<double>(c.k);
   bool have = false;
-  uint32_t pos = 0;
   int32_t ind = 0;
   double r = 0.0, O = 0.0;
   uint64_t P = 0;
@@ -812,7 +810,6 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
     // (a) probe pass
     if (!draining && more && kQueueCap - (qtail - qhead) >= kWave) {
       const bool inb = pbase + lane < c.n;
-      const int e = pf_p;          // position in the vector
       const float wv = pf_w;
       const int32_t pi = pf_i;
       int nb = 0;
@@ -830,14 +827,16 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
       int32_t pj = 1;
       if (inb && wv > 0.0f) {
         pP = mix(c.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(pi)));
+        // (the first target does not depend on the arrival's time: drawn
+        // ahead of its logarithm)
+        pj = randint(draw(pP, kTagShuffle, 1u), 1, c.k);
         pr = 1.0 / static_cast<double>(wv);
         pO = fma(exp1(draw(pP, kTagArrival, 1u)), c1, 0.0);
         const double t = pO * pr;
         ++arrivals;
         if (t <= T) {
           ++kept;
-          pj = randint(draw(pP, kTagShuffle, 1u), 1, c.k);
-          reg_update(c, pj - 1, t, static_cast<uint32_t>(e), pi);
+          reg_update(c, pj - 1, t, pi);
           // Arrivals still to come before T arrive at rate about k v: a walk
           // expected to outgrow the lane's table goes to the segment path.
           const bool longwalk =
@@ -853,7 +852,6 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
         hr->P = pP;
         hr->r = pr;
         hr->O = pO;
-        hr->pos = e;
         hr->ind = pi;
         hr->z = 1;
         hr->nent = pj != 1 ? 1 : 0;
@@ -866,7 +864,6 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
         q.P[slot] = pP;
         q.r[slot] = pr;
         q.O[slot] = pO;
-        q.pos[slot] = static_cast<uint32_t>(e);
         q.ind[slot] = pi;
         q.j1[slot] = static_cast<uint32_t>(pj);
       }
@@ -884,7 +881,6 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
           P = q.P[slot];
           r = q.r[slot];
           O = q.O[slot];
-          pos = q.pos[slot];
           ind = q.ind[slot];
           const uint32_t j1 = q.j1[slot];
           if (O * r <= T) {
@@ -908,8 +904,12 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
     if (any_have) {
       if (have) {
         ++z;
-        // the home slot of position z, read ahead of the arrival's draw
+        // The step's target and the home slots of positions z and j do not
+        // depend on the arrival's time: drawn and read ahead of its
+        // logarithm, off the chain that decides whether the walk goes on.
         const uint32_t hz = mp[map_home(static_cast<uint32_t>(z)) * kWave];
+        const int32_t j = randint(draw(P, kTagShuffle, static_cast<uint32_t>(z)), z, c.k);
+        const uint32_t hj = mp[map_home(static_cast<uint32_t>(j)) * kWave];
         const double E = exp1(draw(P, kTagArrival, static_cast<uint32_t>(z)));
         const double On = fma(E, recip_step(c.k - z + 1), O);
         const double t = On * r;
@@ -920,8 +920,6 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
           have = false;
         } else {
           ++kept;
-          const int32_t j = randint(draw(P, kTagShuffle, static_cast<uint32_t>(z)), z, c.k);
-          const uint32_t hj = mp[map_home(static_cast<uint32_t>(j)) * kWave];
           int zslot, jslot;
           bool zfound, jfound;
           const uint32_t vz = map_find(mp, lm, static_cast<uint32_t>(z), hz, zslot, zfound);
@@ -938,7 +936,7 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
             have = false;
           } else {
             O = On;
-            pend_pk = packed_key(c, t, pos);
+            pend_pk = packed_key(c, t, ind);
             pend_old = reg_offer(c, static_cast<int32_t>(vj) - 1, t, pend_pk, ind);
             pend = c.mode == kWalkNormal;
             if (z == c.k) have = false;
@@ -956,7 +954,6 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
       hr->P = P;
       hr->r = r;
       hr->O = O;
-      hr->pos = static_cast<int32_t>(pos);
       hr->ind = ind;
       hr->z = z - 1;
       int ne = 0;
@@ -1235,8 +1232,6 @@ __device__ bool sketch_vector(const FastArgs& fa, int64_t v, BigInfo* bi, FgShar
   c.seg_rest = fa.seg_rest;
   c.stats = fa.stats;
   if (tid == 0) stat_add(fa.stats, kStVectors, 1);
-  // Positions that do not fit the packed word: resolve indices exactly.
-  if (tid == 0 && n64 >= (1ll << fa.pos_bits)) sh.contest = 1;
   lds_i32* cursor = (lds_i32*)(&sh.cursor);
 
   // Walk with the closed-form threshold; repeat with a larger one while a
@@ -1304,40 +1299,26 @@ __device__ bool sketch_vector(const FastArgs& fa, int64_t v, BigInfo* bi, FgShar
     c.mode = kWalkResolve;
     T = bitsd(ystar);
   }
+  // Write back: the winner's index is the packed word's low bits (after a
+  // resolve walk, the whole word).  An update keeps the lexicographic
+  // (value, index) minimum with the stored register (a part of a split walk
+  // leaves that to the merge; a register an update's cap left empty keeps
+  // its stored value).
   const unsigned long long pmask = (1ull << fa.pos_bits) - 1ull;
-  // gather the winners' indices four registers at a time (loads in flight
-  // together), then store
-  constexpr int kU = 4;
-  for (int j0 = tid; j0 < d.k; j0 += kU * kBlock) {
-    int32_t oi[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int j = j0 + u * kBlock;
-      if (j < d.k) {
-        // (a register an update's cap left empty has no winner to look up)
-        const unsigned long long pk = packed[j];
-        oi[u] = resolve ? static_cast<int32_t>(pk)
-                        : (fullkey[j] != kInfBits ? c.idx[pk & pmask] : kIdxEmpty);
-      }
+  for (int j = tid; j < d.k; j += kBlock) {
+    const unsigned long long pk = packed[j];
+    const unsigned long long fk = fullkey[j];
+    const int32_t oi = resolve ? static_cast<int32_t>(pk)
+                               : (fk != kInfBits ? static_cast<int32_t>(pk & pmask) : kIdxEmpty);
+    bool take = true;
+    if (fa.update && !pt) {
+      const int32_t si = p.out_idx[d.o + j];
+      const unsigned long long sv = dbits(p.out_val[d.o + j]);
+      take = fk != kInfBits && (si < 0 || fk < sv || (fk == sv && oi < si));
     }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int j = j0 + u * kBlock;
-      if (j < d.k) {
-        const unsigned long long fk = fullkey[j];
-        bool take = true;
-        if (fa.update && !pt) {
-          // lexicographic (value, index) minimum with the stored register
-          // (a part of a split walk leaves that to the merge)
-          const int32_t si = p.out_idx[d.o + j];
-          const unsigned long long sv = dbits(p.out_val[d.o + j]);
-          take = fk != kInfBits && (si < 0 || fk < sv || (fk == sv && oi[u] < si));
-        }
-        if (take) {
-          oidx[obase + j] = oi[u];
-          oval[obase + j] = bitsd(fk);
-        }
-      }
+    if (take) {
+      oidx[obase + j] = oi;
+      oval[obase + j] = bitsd(fk);
     }
   }
   group_sync<GW>();
@@ -1412,9 +1393,8 @@ __device__ __forceinline__ void class_body(const FastArgs& fa) {
   q.P = reinterpret_cast<lds_u64*>(wave_base);
   q.r = reinterpret_cast<lds_f64*>(wave_base + kQueueCap * 8);
   q.O = reinterpret_cast<lds_f64*>(wave_base + kQueueCap * 16);
-  q.pos = reinterpret_cast<lds_u32*>(wave_base + kQueueCap * 24);
-  q.ind = reinterpret_cast<lds_i32*>(wave_base + kQueueCap * 28);
-  q.j1 = reinterpret_cast<lds_u32*>(wave_base + kQueueCap * 32);
+  q.ind = reinterpret_cast<lds_i32*>(wave_base + kQueueCap * 24);
+  q.j1 = reinterpret_cast<lds_u32*>(wave_base + kQueueCap * 28);
   lds_u32* mp_base = reinterpret_cast<lds_u32*>(wave_base + queue_bytes());
   // the segment path's permutations reuse the same bytes
   lds_u16* pm = reinterpret_cast<lds_u16*>(wave_base);

@@ -88,10 +88,11 @@ def test_host_side_argument_validation(lib):
 def test_options_validation(lib):
     from paper_2302_05176_amd import _native as N
     assert lib.gm_set_option(0, 7) == N.GM_ERR_INVALID_ARG
+    assert lib.gm_set_option(0, 30) == N.GM_ERR_INVALID_ARG
     assert lib.gm_set_option(2, 17) == N.GM_ERR_INVALID_ARG
     assert lib.gm_set_option(3, 3) == N.GM_ERR_INVALID_ARG
     assert lib.gm_set_option(99, 1) == N.GM_ERR_INVALID_ARG
-    assert lib.gm_set_option(0, 24) == N.GM_OK
+    assert lib.gm_set_option(0, 31) == N.GM_OK
     assert lib.gm_set_option(3, 4) == N.GM_OK
     # timing: 0 off, 1 every launch, 2 the sketch kernels only
     assert lib.gm_set_option(7, 3) == N.GM_ERR_INVALID_ARG
