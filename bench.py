@@ -140,7 +140,7 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.document_batch.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.all_workloads.txt")
 
 
 def committed_traffic(kernel: str, workload: str):
@@ -195,25 +195,52 @@ def summarize_pmc(args):
     for e in out.values():
         e["bytes_per_launch"] = e.get("fetch_size_bytes", 0.0) + e.get("write_size_bytes", 0.0)
         e["source_sha256"] = source_digest()
-    workload = f"batch_k{args.k}_{args.form}"
+    workload = traffic_key(args)
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         rec = {}
     rec[workload] = {n: e for n, e in out.items() if "elementwise" not in n and "__amd" not in n}
-    rec["_commands"] = [
-        "cd /tmp && timeout -s KILL 90 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc_FETCH_SIZE -o run -- "
-        "python3 <repo>/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras --copy-bytes 1073741824",
-        "cd /tmp && timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <repo>/gpurun_out/pmc_WRITE_SIZE -o run -- "
-        "python3 <repo>/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras --copy-bytes 1073741824",
-        "python bench.py --summarize-pmc gpurun_out/pmc_FETCH_SIZE gpurun_out/pmc_WRITE_SIZE --copy-bytes 1073741824 --k 256",
+    wl = "" if args.workload == "batch" else f" --workload {args.workload}"
+    extra = (" --steps 3 --warmup 1 --no-cpu-baseline --no-extras" if args.workload == "batch"
+             else " --steps 2 --warmup 1 --no-autotune")
+    rec.setdefault("_commands", {})
+    if isinstance(rec["_commands"], list):
+        rec["_commands"] = {}
+    rec["_commands"][workload] = [
+        f"cd /tmp && timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc_{workload}_FETCH_SIZE -o run -- "
+        f"python3 <repo>/bench.py{wl}{extra} --copy-bytes 1073741824",
+        f"cd /tmp && timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <repo>/gpurun_out/pmc_{workload}_WRITE_SIZE -o run -- "
+        f"python3 <repo>/bench.py{wl}{extra} --copy-bytes 1073741824",
+        f"python bench.py{wl} --summarize-pmc gpurun_out/pmc_{workload}_FETCH_SIZE gpurun_out/pmc_{workload}_WRITE_SIZE "
+        f"--copy-bytes 1073741824 --k {args.k}",
         "FETCH_SIZE and WRITE_SIZE are KiB per dispatch; each is scaled by copy_bytes / (what it reads for the "
         "calibration elementwise kernel that reads and writes copy_bytes)"]
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1, sort_keys=True)
         f.write("\n")
     print(json.dumps(rec[workload], indent=1))
+
+
+def traffic_key(args) -> str:
+    """Key of a workload's entry in the committed traffic record."""
+    if args.workload == "batch":
+        return f"batch_k{args.k}_{args.form}"
+    return args.workload
+
+
+def calibration_copy(args):
+    """Counter calibration: one elementwise kernel that reads and writes
+    copy_bytes each (FETCH_SIZE and WRITE_SIZE are scaled by it)."""
+    if not args.copy_bytes:
+        return
+    import torch
+    a = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def parse():
@@ -232,6 +259,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall seconds of oracle work for the CPU baseline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="uneven workload: default schedule options instead of gm_autotune's")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device copy of this many bytes (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -303,14 +332,7 @@ def bench_batch(args):
     out_v = torch.empty((args.nvec, k), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     gm.reset_options()
-    if args.copy_bytes:
-        # counter calibration: one elementwise kernel that reads and writes
-        # copy_bytes each
-        a = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        torch.mul(a, 2.0, out=b)
-        torch.cuda.synchronize()
-        del a, b
+    calibration_copy(args)
     step = lambda kk=k, form=args.form, oi=out_i, ov=out_v: gm.sketch(
         ti, tw, to, kk, args.seed, form=form, out_idx=oi, out_val=ov)
     # Timed region: HIP events around the sketch kernels only (timing level
@@ -426,6 +448,11 @@ def bench_single(args):
                       "results": res}), flush=True)
 
 
+def kernel_traffic(name, workload):
+    """Committed HBM bytes per launch of the kernel a timing entry names."""
+    return committed_traffic(name.split(" [")[0], workload)
+
+
 def stream_kernel_rooflines(breakdown, n, k):
     """Roofline entries of the kernels of one stream-vector sketch (n entries,
     one vector of more than 32768 entries): the weight sum (4 bytes per
@@ -434,23 +461,25 @@ def stream_kernel_rooflines(breakdown, n, k):
     candidate walk (k H_k arrivals beyond the first ones)."""
     ent = {}
     for name, ms in breakdown.items():
+        tr = kernel_traffic(name, "stream")
         if name.startswith("big_sum_kernel"):
-            ent[name] = kernel_roofline(name, ms, hbm_bytes=4.0 * n, bound="hbm")
+            ent[name] = kernel_roofline(name, ms, hbm_bytes=4.0 * n, bound="hbm", traffic=tr)
         elif name.startswith("big_probe_kernel"):
-            ent[name] = kernel_roofline(name, ms, hbm_bytes=8.0 * n, bound="hbm")
+            ent[name] = kernel_roofline(name, ms, hbm_bytes=8.0 * n, bound="hbm", traffic=tr)
         elif name.startswith("fastgm_big_kernel"):
             ent[name] = kernel_roofline(name, ms, k * harmonic(k), ARRIVAL_SLOTS,
                                         "arrivals (k H_k beyond the first arrivals)",
-                                        hbm_bytes=12.0 * k, bound="alu")
+                                        hbm_bytes=12.0 * k, bound="alu", traffic=tr)
     return ent
 
 
 def bench_stream(args):
     """One vector of 10^7 entries, k = 1024 and 4096.  The headline of the
-    line is k = 1024; each k reports its step time, the per-kernel roofline
-    entries (HIP events around every launch, on the call's stream, inside the
-    timed loop), the cardinality estimator over 100 seeds, and the plain
-    form's time for the FastGM/plain ratio."""
+    line is k = 1024; each k reports its step time (no events inside the
+    timed loop), the per-kernel roofline entries (HIP events around every
+    launch, on the call's stream, over a second pass of as many steps), the
+    cardinality estimator over 100 seeds, and the plain form's time for the
+    FastGM/plain ratio."""
     import numpy as np
     import torch
 
@@ -462,15 +491,19 @@ def bench_stream(args):
     ti, tw, to = (torch.from_numpy(a).to(dev) for a in (idx, w, off))
     stream = torch.cuda.current_stream()
     S = float(w.astype("float64").sum())
+    calibration_copy(args)
     out = {}
     for k in (1024, 4096):
         step = lambda kk=k: gm.sketch(ti, tw, to, kk, args.seed)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
+        ms, _ = timed_steps(step, args.steps, 0, stream)
+        # the breakdown in a pass of its own: the events around every launch
+        # cost a few microseconds each, a noticeable share of a 0.15 ms step
         gm.set_option("timing", 1)
         gm.reset_timing()
-        ms, _ = timed_steps(step, args.steps, 0, stream)
+        timed_steps(step, args.steps, 0, stream)
         breakdown = per_kernel_ms(gm.get_timing())
         gm.set_option("timing", 0)
         kern = stream_kernel_rooflines(breakdown, n, k)
@@ -556,10 +589,13 @@ def uneven_kernel_rooflines(breakdown, n, kk):
     small = n <= SMALL_LIMIT
     ent = {}
     for name, ms in breakdown.items():
+        tr = kernel_traffic(name, "uneven")
         if name.startswith("big_sum_kernel"):
-            ent[name] = kernel_roofline(name, ms, hbm_bytes=4.0 * n[~small].sum(), bound="hbm")
+            ent[name] = kernel_roofline(name, ms, hbm_bytes=4.0 * n[~small].sum(), bound="hbm",
+                                        traffic=tr)
         elif name.startswith("big_probe_kernel"):
-            ent[name] = kernel_roofline(name, ms, hbm_bytes=8.0 * n[~small].sum(), bound="hbm")
+            ent[name] = kernel_roofline(name, ms, hbm_bytes=8.0 * n[~small].sum(), bound="hbm",
+                                        traffic=tr)
         elif "[class " in name:
             c = int(name.split("class ")[1].rstrip("]"))
             sel = (kcls == c % 4) & (small if c < 4 else ~small)
@@ -573,7 +609,7 @@ def uneven_kernel_rooflines(breakdown, n, kk):
                 units = float((kk[sel] * hv[sel]).sum())
                 uname = "arrivals (k H_k per big vector, beyond the first arrivals)"
                 byt = 12.0 * kk[sel].sum() + 12.0 * sel.sum()
-            ent[name] = kernel_roofline(name, ms, units, ARRIVAL_SLOTS, uname, byt, "alu")
+            ent[name] = kernel_roofline(name, ms, units, ARRIVAL_SLOTS, uname, byt, "alu", traffic=tr)
     return ent
 
 
@@ -595,11 +631,16 @@ def bench_uneven(args):
     total = int(outoff[-1])
     oi = torch.empty(total, dtype=torch.int32, device=dev)
     ov = torch.empty(total, dtype=torch.float64, device=dev)
+    calibration_copy(args)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         gm.reserve(nvec, stream=s)
-        tuned = gm.autotune(ti, tw, to, 4096, args.seed, k_per_vec=tk, out_offsets=too,
-                            out_idx=oi, out_val=ov, reps=1, stream=s)
+        if args.no_autotune:
+            gm.reset_options()
+            tuned = None
+        else:
+            tuned = gm.autotune(ti, tw, to, 4096, args.seed, k_per_vec=tk, out_offsets=too,
+                                out_idx=oi, out_val=ov, reps=1, stream=s)
     s.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):

@@ -49,9 +49,9 @@ constexpr int kMaxDevices = 64;
 
 // Planner workspace of one (device, stream): the vector list and the class
 // counters.  Keyed by stream so that calls on different streams never share it.
-// Candidate-list pool of the big vectors (entries): 128 MiB.  A big vector
+// Candidate-list pool of the big vectors (entries): 256 MiB.  A big vector
 // that does not fit is walked over all of its entries instead.
-constexpr int64_t kPoolCap = 32ll << 20;
+constexpr int64_t kPoolCap = 64ll << 20;
 
 struct PlanWorkspace {
   int32_t* list = nullptr;

@@ -141,14 +141,31 @@ constexpr int64_t kPartRegs = static_cast<int64_t>(kSplitMaxBig) * kMaxParts * G
 
 constexpr int kSumSlots = 16;  // partial sums of a big vector's weights
 
+// The probe pass lists a big vector's candidates in kCandLists sublists,
+// work item u in sublist u mod kCandLists, each with a counter of its own
+// 128-byte line at the head of the vector's pool region; the gather pass
+// then packs them into one list.  (A returning atomic on one address takes
+// tens of nanoseconds and every work item's would queue behind the
+// others'.)  A sublist that fills up passes its excess to the list itself,
+// through one counter (over_count).
+constexpr int kCandLists = 16;
+constexpr int kCntStride = 32;  // int32 words between two counters
+constexpr int64_t kCandHeader = static_cast<int64_t>(kCandLists) * kCntStride;
+// A big vector gets a candidate list when the list's room is at most this
+// fraction of its entries.
+constexpr double kListFrac = 0.8;
+
 struct BigInfo {
   int64_t chunk_base;    // first chunk of this vector
   int64_t cand_off;      // offset of its candidate list in the pool
+  int64_t sub_off;       // offset of its kCandLists sublists (the probe's output)
   double S;              // sum of weights: the slots added in order (by the probe pass)
   int bad;               // invalid weight seen (sum pass)
   int bad_index;         // negative index seen (probe pass; read after it)
-  int cand_count;        // candidates found (may exceed cand_cap)
+  int cand_count;        // candidates found (may exceed cand_cap; set by the gather pass)
   int cand_cap;          // room in the pool (0: no list, walk everything)
+  int sub_cap;           // room in each sublist
+  int over_count;        // candidates past a full sublist, listed at the list's start
   int parts_done;        // parts of a split walk that have written their sketch
   int64_t part_off;      // first scratch register of its parts (kMaxParts x k_max)
   // chunk sums, added atomically into one of kSumSlots slots (one slot per
@@ -1486,8 +1503,12 @@ void fastgm_class_kernel(FastArgs fa) {
   class_body<W, G, false>(fa);
 }
 
+// The big-vector kernels walk few vectors, a split walk's parts one
+// workgroup each: they run at two waves per SIMD without spills.  (With
+// spills, even a launch with no big vector wrote each lane's spill slots
+// before it could exit: 16 MiB per call.)
 template <int W, int G>
-__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(class_waves_per_eu<G>())))
+__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(2)))
 void fastgm_big_kernel(FastArgs fa) {
   class_body<W, G, true>(fa);
 }
@@ -1508,7 +1529,7 @@ __device__ __forceinline__ int plan_bin(const SketchArgs& p, int64_t v, int64_t 
 
 __global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t* list,
                                                           PlanState* plan, BigInfo* big,
-                                                          int64_t pool_cap, double t0_scale,
+                                                          int32_t* pool, int64_t pool_cap, double t0_scale,
                                                           int64_t lim_m) {
   __shared__ int hist[kNumClasses * kPlanBins];
   __shared__ int base[kNumClasses * kPlanBins];
@@ -1560,11 +1581,17 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t*
       if (k >= 1 && k <= p.k_max) {
         const double x = static_cast<double>(k) * max_exp_quantile(k) * (t0_scale > 1.0 ? t0_scale : 1.0);
         const int64_t c = static_cast<int64_t>(1.25 * x + 4.0 * sqrt(x) + 256.0);
-        cap = c < n ? c : n;
+        // a list that may hold most of the entries saves the walk little
+        // and the probe's first arrivals would all be drawn twice: such a
+        // vector is walked over all its entries
+        cap = static_cast<double>(c) <= kListFrac * static_cast<double>(n) ? c : 0;
       }
     }
+    // pool region: sublist counters, sublists, the list
+    const int64_t scap = ((cap + kCandLists - 1) / kCandLists + 31) / 32 * 32;
+    const int64_t region = cap > 0 ? kCandHeader + kCandLists * scap + cap : 0;
     sc_ch[tid] = nch;
-    sc_cap[tid] = cap;
+    sc_cap[tid] = region;
     __syncthreads();
     for (int d = 1; d < kPlanBlock; d <<= 1) {
       const int64_t a1 = tid >= d ? sc_ch[tid - d] : 0;
@@ -1577,13 +1604,19 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(SketchArgs p, int32_t*
     if (i < c2) {
       BigInfo bi;
       bi.chunk_base = run_ch + sc_ch[tid] - nch;
-      bi.cand_off = run_cap + sc_cap[tid] - cap;
+      const int64_t r0 = run_cap + sc_cap[tid] - region;
+      bi.sub_off = r0 + kCandHeader;
+      bi.cand_off = bi.sub_off + kCandLists * scap;
       bi.S = 0.0;
       for (int q = 0; q < kSumSlots; ++q) bi.Sslot[q] = 0.0;
       bi.bad = 0;
       bi.bad_index = 0;
       bi.cand_count = 0;
-      bi.cand_cap = (bi.cand_off + cap <= pool_cap) ? static_cast<int>(cap) : 0;
+      bi.cand_cap = (cap > 0 && r0 + region <= pool_cap) ? static_cast<int>(cap) : 0;
+      bi.sub_cap = static_cast<int>(scap);
+      bi.over_count = 0;
+      if (bi.cand_cap > 0)
+        for (int q = 0; q < kCandLists; ++q) pool[r0 + q * kCntStride] = 0;
       bi.parts_done = 0;
       bi.part_off = static_cast<int64_t>(i) * kMaxParts * GM_K_MAX;
       big[i] = bi;
@@ -1615,6 +1648,14 @@ __device__ __forceinline__ int big_of_chunk(const BigInfo* big, int c2, int64_t 
 }
 
 constexpr int kBigBlock = 256;
+// Work items of the probe pass: kProbeSplit per chunk, kProbeUnroll entries
+// per lane.
+constexpr int kProbeUnroll = 16;
+constexpr int kProbeItem = kBigBlock * kProbeUnroll;
+constexpr int kProbeSplit = static_cast<int>(kBigChunk / kProbeItem);
+static_assert(kBigChunk % kProbeItem == 0, "probe items tile a chunk");
+constexpr int kProbeWgPerCu = 8;  // workgroups per CU of a probe launch
+constexpr int kProbeWaves = 4;    // waves per SIMD the probe is compiled for
 
 // Single-precision rejection of a first arrival.  The probe keeps an entry
 // when O_1 <= bound v, O_1 = RN(E_1 RN(1/k)) and E_1 = -ln u.  With
@@ -1697,131 +1738,220 @@ __global__ __launch_bounds__(kBigBlock) void big_sum_kernel(FastArgs fa) {
 
 // Grid-wide pass 2 over big vectors: first arrival of every entry; entries
 // within T0 go to the vector's candidate list.
-__global__ __launch_bounds__(kBigBlock) void big_probe_kernel(FastArgs fa) {
-  __shared__ int32_t slist[kBigChunk];
-  __shared__ int scount, sbase;
+//
+// The pass is bound by its arithmetic (two splitmix64 rounds per entry,
+// twelve quarter-rate 32-bit multiplies), not by HBM.  Its work items are
+// parts of chunks, kProbeItem entries, kProbeUnroll per lane with every
+// load issued at once; a workgroup takes a contiguous run of items.  Each
+// item's candidates join one of the vector's kCandLists sublists.
+__global__ __launch_bounds__(kBigBlock) __attribute__((amdgpu_waves_per_eu(kProbeWaves)))
+void big_probe_kernel(FastArgs fa) {
+  __shared__ int32_t mlist[kProbeItem];  // entries the first round kept
+  __shared__ int32_t slist[kProbeItem];  // candidates
+  __shared__ int smaybe, scount, sbase, sover;
+  __shared__ unsigned long long smax[kBigBlock / kWave];
+  __shared__ int sempty;
   const SketchArgs& p = fa.s;
   int c2 = 0;
   for (int cc = kBigFirst; cc < kNumClasses; ++cc) c2 += fa.plan->count[cc];
   const int32_t* list2 = fa.list + fa.plan->offset[kBigFirst];
-  const int64_t total = fa.plan->big_chunks;
+  const int64_t nchunks = fa.plan->big_chunks;
+  const int64_t total = nchunks * kProbeSplit;
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const int b = big_of_chunk(fa.big, c2, t);
-    const VecDesc d = vec_desc(p, list2[b]);
-    BigInfo* bi = &fa.big[b];
-    double S = 0.0;
-    for (int q = 0; q < kSumSlots; ++q) S += bi->Sslot[q];
-    // (every block of the vector computes the same S; later launches read it)
-    if (tid == 0 && t == bi->chunk_base) bi->S = S;
-    if (d.bad || bi->bad) continue;  // poisoned already
-    if (!(S > 0.0) || bi->cand_cap <= 0) {
-      // no candidate list (no positive weight, or no room in the pool):
-      // only the indices are checked here
-      const int64_t e0 = d.a + (t - bi->chunk_base) * kBigChunk;
-      const int64_t e1 = e0 + kBigChunk < d.b ? e0 + kBigChunk : d.b;
+  // Each workgroup takes a contiguous run of items, so that consecutive
+  // items mostly share a vector and its state below is looked up once.
+  const int64_t u0 = total * blockIdx.x / gridDim.x;
+  const int64_t u1 = total * (blockIdx.x + 1) / gridDim.x;
+  int b = -1;
+  int64_t next_vec_item = -1;  // first item of the vector after b
+  VecDesc d{};
+  BigInfo* bi = nullptr;
+  int mode = 0;  // 0 nothing to do, 1 indices only, 2 candidates
+  double S = 0.0, c1 = 0.0, bound = 0.0;
+  float kbl = 0.0f;
+  for (int64_t u = u0; u < u1; ++u) {
+    const int64_t t = u / kProbeSplit;
+    if (u >= next_vec_item) {
+      b = big_of_chunk(fa.big, c2, t);
+      bi = &fa.big[b];
+      d = vec_desc(p, list2[b]);
+      next_vec_item = (b + 1 < c2 ? fa.big[b + 1].chunk_base : nchunks) * kProbeSplit;
+      S = 0.0;
+      for (int q = 0; q < kSumSlots; ++q) S += bi->Sslot[q];
+      if (d.bad || bi->bad) {
+        mode = 0;  // poisoned already
+      } else if (!(S > 0.0) || bi->cand_cap <= 0) {
+        // no candidate list (no positive weight, a list not worth keeping,
+        // or no room in the pool): only the indices are checked here
+        mode = 1;
+      } else {
+        mode = 2;
+        double T0 = max_exp_quantile(d.k) * fa.t0_scale / S;
+        if (fa.update) {
+          // an update's walk stops at the stored sketch's largest register
+          if (tid == 0) sempty = 0;
+          __syncthreads();
+          unsigned long long m = 0;
+          bool empty = false;
+          for (int j = tid; j < d.k; j += kBigBlock) {
+            if (p.out_idx[d.o + j] < 0)
+              empty = true;
+            else
+              m = dbits(p.out_val[d.o + j]) > m ? dbits(p.out_val[d.o + j]) : m;
+          }
+          m = wave_max_u64(m);
+          if (lane == 0) smax[tid / kWave] = m;
+          if (empty) sempty = 1;
+          __syncthreads();
+          unsigned long long ms = 0;
+          for (int qq = 0; qq < kBigBlock / kWave; ++qq) ms = smax[qq] > ms ? smax[qq] : ms;
+          if (!sempty) T0 = fmin(T0, bitsd(ms));
+          __syncthreads();
+        }
+        c1 = 1.0 / static_cast<double>(d.k);
+        // The walk keeps an element when RN(O_1 RN(1/v)) <= T (T <= T0),
+        // which implies O_1 <= T0 v (1 + 2^-51.9); the test below, with two
+        // roundings of its own, admits at least that and needs no division.
+        bound = T0 * (1.0 + 0x1p-50);
+        kbl = rejection_scale(d.k, bound);
+      }
+    }
+    // (every workgroup of the vector computes the same S; later launches read it)
+    if (tid == 0 && u == bi->chunk_base * kProbeSplit) bi->S = S;
+    const int qpart = static_cast<int>(u - t * kProbeSplit);
+    const int64_t e0 = d.a + (t - bi->chunk_base) * kBigChunk + static_cast<int64_t>(qpart) * kProbeItem;
+    if (mode == 0 || e0 >= d.b) continue;  // (past the end of the vector's last chunk)
+    const int64_t e1 = e0 + kProbeItem < d.b ? e0 + kProbeItem : d.b;
+    if (mode == 1) {
       bool badi = false;
       for (int64_t e = e0 + tid; e < e1; e += kBigBlock) badi |= p.idx[e] < 0;
       if (__ballot(badi) != 0 && lane == 0) atomicOr(&bi->bad_index, 1);
       continue;
     }
-    double T0 = max_exp_quantile(d.k) * fa.t0_scale / S;
-    if (fa.update) {
-      // an update's walk stops at the stored sketch's largest register
-      __shared__ unsigned long long smax[kBigBlock / kWave];
-      __shared__ int sempty;
-      if (tid == 0) sempty = 0;
-      __syncthreads();
-      unsigned long long m = 0;
-      bool empty = false;
-      for (int j = tid; j < d.k; j += kBigBlock) {
-        if (p.out_idx[d.o + j] < 0)
-          empty = true;
-        else
-          m = dbits(p.out_val[d.o + j]) > m ? dbits(p.out_val[d.o + j]) : m;
-      }
-      m = wave_max_u64(m);
-      if (lane == 0) smax[tid / kWave] = m;
-      if (empty) sempty = 1;
-      __syncthreads();
-      unsigned long long ms = 0;
-      for (int qq = 0; qq < kBigBlock / kWave; ++qq) ms = smax[qq] > ms ? smax[qq] : ms;
-      if (!sempty) T0 = fmin(T0, bitsd(ms));
-      __syncthreads();
+    // Two rounds per item.  First every entry's first arrival is drawn and
+    // the single-precision test rejects all but a few (about 0.2 % at
+    // k = 1024); the rest are listed in LDS.  Then the workgroup's lanes take
+    // the listed entries densely and apply the exact test in double
+    // precision; the candidates go to a second LDS list, which one of the
+    // vector's sublists takes with one atomic.  Keeping the logarithm out of
+    // the unrolled round keeps the kernel small enough for many resident
+    // waves.
+    if (tid == 0) {
+      smaybe = 0;
+      scount = 0;
     }
-    const double c1 = 1.0 / static_cast<double>(d.k);
-    // The walk keeps an element when RN(O_1 RN(1/v)) <= T (T <= T0), which
-    // implies O_1 <= T0 v (1 + 2^-51.9); the test below, with two roundings
-    // of its own, admits at least that and needs no division.
-    const double bound = T0 * (1.0 + 0x1p-50);
-    const float kbl = rejection_scale(d.k, bound);
-    const int64_t e0 = d.a + (t - bi->chunk_base) * kBigChunk;
-    const int64_t e1 = e0 + kBigChunk < d.b ? e0 + kBigChunk : d.b;
-    // The chunk's candidates are gathered in LDS and the vector's list takes
-    // them with one atomic: one counter per vector, hit by every wave, would
-    // serialise the pass.
-    if (tid == 0) scount = 0;
     __syncthreads();
     bool badl = false;
-    // four entries per lane per step, their loads issued together one step
-    // ahead, so that a step's arithmetic hides the next step's loads
-    constexpr int kPU = 4;
-    float wv[kPU], wn[kPU];
-    int32_t iv[kPU], inx[kPU];
-    auto load_step = [&](int64_t eb, float (&wd)[kPU], int32_t (&id)[kPU]) {
+    constexpr int kPU = kProbeUnroll;
+    float wv[kPU];
+    int32_t iv[kPU];
 #pragma unroll
-      for (int u = 0; u < kPU; ++u) {
-        const int64_t e = eb + u * kBigBlock + tid;
-        wd[u] = e < e1 ? p.w[e] : 0.0f;
-        id[u] = e < e1 ? p.idx[e] : 0;
+    for (int q = 0; q < kPU; ++q) {
+      const int64_t e = e0 + q * kBigBlock + tid;
+      wv[q] = e < e1 ? p.w[e] : 0.0f;
+      iv[q] = e < e1 ? p.idx[e] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kPU; ++q) {
+      const int64_t e = e0 + q * kBigBlock + tid;
+      bool maybe = false;
+      if (iv[q] < 0) badl = true;
+      if (wv[q] > 0.0f) {
+        const uint64_t P = mix(p.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(iv[q])));
+        maybe = !surely_late(draw(P, kTagArrival, 1u), kbl, wv[q]);
       }
-    };
-    load_step(e0, wv, iv);
-    for (int64_t eb = e0; eb < e1; eb += kPU * kBigBlock) {
-      load_step(eb + kPU * kBigBlock, wn, inx);
-#pragma unroll
-      for (int u = 0; u < kPU; ++u) {
-        const int64_t e = eb + u * kBigBlock + tid;
-        bool cand = false;
-        if (iv[u] < 0) badl = true;
-        if (wv[u] > 0.0f) {
-          const uint64_t P = mix(p.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(iv[u])));
-          const uint64_t x = draw(P, kTagArrival, 1u);
-          // most entries are rejected in single precision, without the log
-          if (!surely_late(x, kbl, wv[u])) {
-            const double O1 = fma(exp1(x), c1, 0.0);
-            cand = O1 <= bound * static_cast<double>(wv[u]);
-          }
-        }
-        const uint64_t m = __ballot(cand);
-        if (m) {
-          const int leader = __ffsll(static_cast<long long>(m)) - 1;
-          int base = 0;
-          if (lane == leader) base = atomicAdd(&scount, __popcll(m));
-          base = readlane_i32(base, leader);
-          // (at most kBigChunk candidates per chunk: the list always has room)
-          if (cand) slist[base + __popcll(m & lanemask_lt())] = static_cast<int32_t>(e - d.a);
-        }
+      const uint64_t m = __ballot(maybe);
+      if (m) {
+        const int leader = __ffsll(static_cast<long long>(m)) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&smaybe, __popcll(m));
+        base = readlane_i32(base, leader);
+        // (at most kProbeItem entries per item: the lists always have room)
+        if (maybe) mlist[base + __popcll(m & lanemask_lt())] = static_cast<int32_t>(e - d.a);
       }
-#pragma unroll
-      for (int u = 0; u < kPU; ++u) {
-        wv[u] = wn[u];
-        iv[u] = inx[u];
+    }
+    __syncthreads();
+    const int nm = smaybe;
+    for (int r = 0; r < nm; r += kBigBlock) {
+      bool cand = false;
+      int32_t rel = 0;
+      if (r + tid < nm) {
+        rel = mlist[r + tid];
+        const float w = p.w[d.a + rel];
+        const uint64_t P = mix(p.seed_mix ^ static_cast<uint64_t>(static_cast<uint32_t>(p.idx[d.a + rel])));
+        const double O1 = fma(exp1(draw(P, kTagArrival, 1u)), c1, 0.0);
+        cand = O1 <= bound * static_cast<double>(w);
+      }
+      const uint64_t m = __ballot(cand);
+      if (m) {
+        const int leader = __ffsll(static_cast<long long>(m)) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&scount, __popcll(m));
+        base = readlane_i32(base, leader);
+        if (cand) slist[base + __popcll(m & lanemask_lt())] = rel;
       }
     }
     // a negative index poisons the vector (the walk reads the flag; this
-    // pass never does, so its blocks take the same branches)
+    // pass never does, so its workgroups take the same branches)
     if (__ballot(badl) != 0 && lane == 0) atomicOr(&bi->bad_index, 1);
     __syncthreads();
     const int nc = scount;
-    if (tid == 0 && nc > 0) sbase = atomicAdd(&bi->cand_count, nc);
-    __syncthreads();
-    for (int q = tid; q < nc; q += kBigBlock) {
-      const int slot = sbase + q;
-      if (slot < bi->cand_cap) fa.pool[bi->cand_off + slot] = slist[q];
+    if (nc > 0) {
+      // the item's sublist takes what it has room for, the list the rest
+      const int scap = bi->sub_cap;
+      const int ql = static_cast<int>((u - bi->chunk_base * kProbeSplit) % kCandLists);
+      int32_t* subl = fa.pool + bi->sub_off + static_cast<int64_t>(ql) * scap;
+      if (tid == 0) {
+        const int b0 = atomicAdd(fa.pool + bi->sub_off - kCandHeader + ql * kCntStride, nc);
+        const int fit = b0 >= scap ? 0 : (scap - b0 < nc ? scap - b0 : nc);
+        sbase = b0;
+        sover = fit < nc ? atomicAdd(&bi->over_count, nc - fit) - fit : 0;
+      }
+      __syncthreads();
+      const int b0 = sbase;
+      for (int q = tid; q < nc; q += kBigBlock) {
+        if (b0 + q < scap) {
+          subl[b0 + q] = slist[q];
+        } else {
+          const int slot = sover + q;  // (over_count + q - fit)
+          if (slot < bi->cand_cap) fa.pool[bi->cand_off + slot] = slist[q];
+        }
+      }
     }
     __syncthreads();
+  }
+}
+
+// Gather pass: each big vector's sublists packed after the entries that
+// overflowed into its list; cand_count set to the total, or past cand_cap
+// if the list cannot hold them all (the walk then takes every entry).
+// Work items are (vector, sublist) pairs.
+__global__ __launch_bounds__(kBigBlock) void big_gather_kernel(FastArgs fa) {
+  int c2 = 0;
+  for (int cc = kBigFirst; cc < kNumClasses; ++cc) c2 += fa.plan->count[cc];
+  const int64_t total = static_cast<int64_t>(c2) * kCandLists;
+  const int tid = threadIdx.x;
+  for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    const int b = static_cast<int>(u / kCandLists);
+    const int q = static_cast<int>(u - static_cast<int64_t>(b) * kCandLists);
+    BigInfo* bi = &fa.big[b];
+    if (bi->cand_cap <= 0) continue;
+    const int scap = bi->sub_cap;
+    const int32_t* cnt = fa.pool + bi->sub_off - kCandHeader;
+    int64_t at = bi->over_count, all = at;
+    for (int r = 0; r < kCandLists; ++r) {
+      const int m = cnt[r * kCntStride] < scap ? cnt[r * kCntStride] : scap;
+      if (r < q) at += m;
+      all += m;
+    }
+    const bool fits = all <= bi->cand_cap;
+    if (q == 0 && tid == 0) bi->cand_count = fits ? static_cast<int>(all) : bi->cand_cap + 1;
+    if (!fits) continue;
+    const int mq = cnt[q * kCntStride] < scap ? cnt[q * kCntStride] : scap;
+    const int32_t* src = fa.pool + bi->sub_off + static_cast<int64_t>(q) * scap;
+    int32_t* dst = fa.pool + bi->cand_off + at;
+    for (int i = tid; i < mq; i += kBigBlock) dst[i] = src[i];
   }
 }
 
@@ -2044,7 +2174,7 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
   hipEvent_t ta = nullptr;
   int tid = timing_begin("plan_kernel", false, stream, &ta);
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, stream, s, list, fa.plan, fa.big,
-                     pool_cap, t0_scale, kLimM);
+                     pool, pool_cap, t0_scale, kLimM);
   timing_end(tid, ta, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -2052,7 +2182,10 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
   hipLaunchKernelGGL(big_sum_kernel, dim3(cus * 8), dim3(kBigBlock), 0, stream, fa);
   timing_end(tid, ta, stream);
   tid = timing_begin("big_probe_kernel", false, stream, &ta);
-  hipLaunchKernelGGL(big_probe_kernel, dim3(cus * 8), dim3(kBigBlock), 0, stream, fa);
+  hipLaunchKernelGGL(big_probe_kernel, dim3(cus * kProbeWgPerCu), dim3(kBigBlock), 0, stream, fa);
+  timing_end(tid, ta, stream);
+  tid = timing_begin("big_gather_kernel", false, stream, &ta);
+  hipLaunchKernelGGL(big_gather_kernel, dim3(cus * 2), dim3(kBigBlock), 0, stream, fa);
   timing_end(tid, ta, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -347,6 +347,30 @@ def test_big_vectors_candidate_lists(gm, k):
                  oracle.sketch(idx, w, off, k, 21, form=oracle.FORM_STREAM), f"k={k}")
 
 
+@pytest.mark.parametrize("k", [1024, 4096])
+def test_big_vector_skewed_candidates(gm, k):
+    """Candidates packed into a few of the probe pass's work items overflow
+    their sublists into the list itself (the heavy entries lead one vector,
+    trail another; at k = 4096 the shorter vector keeps no list); the
+    gathered lists must walk to the oracle's sketch."""
+    rng = np.random.default_rng(31)
+    rows_i, rows_w = [], []
+    for n, lead in ((200_000, True), (60_000, False)):
+        rows_i.append(W.distinct_sorted(rng, n, 1 << 24))
+        ww = np.full(n, 1e-6, np.float32)
+        heavy = (W.exp1_weights(rng, 6000) * 1000).astype(np.float32)
+        if lead:
+            ww[:6000] = heavy
+        else:
+            ww[-6000:] = heavy
+        rows_w.append(ww)
+    idx, w, off = W._pack(rows_i, rows_w)
+    oracle.set_threads(8)
+    print(f"big vectors, skewed weights, k={k}", flush=True)
+    _assert_same(_gpu_sketch(gm, idx, w, off, k, 24),
+                 oracle.sketch(idx, w, off, k, 24, form=oracle.FORM_STREAM), f"k={k}")
+
+
 @pytest.mark.parametrize("opt,val", [("t0_scale_ppm", 1), ("t0_scale_ppm", 300_000),
                                      ("pos_bits", 56), ("map_load", 0)])
 def test_big_vectors_forced_paths(gm, opt, val):
