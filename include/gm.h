@@ -176,7 +176,7 @@ gm_status gm_reserve(int64_t nvec, hipStream_t stream);
  * gm_workspace_bytes -- device bytes of the workspace that gm_reserve(nvec,
  * stream) creates for one stream on the current device: the FastGM planner
  * list and per-vector records (about 200 bytes per vector), the big-vector
- * candidate pool (128 MiB), the walk's per-wave lists (64 KiB per resident
+ * candidate pool (256 MiB), the walk's per-wave lists (64 KiB per resident
  * wave), the split-walk scratch and the plain form's split scratch.  For
  * admission control: each stream that sketches concurrently holds one.
  * Allocates nothing; nvec in [0, 2^31).
@@ -323,7 +323,10 @@ gm_status gm_reset_data_errors(hipStream_t stream);
  *                        segment path, where 16 or 64 lanes walk it
  *                        together (0 sends almost every element there).
  *   GM_OPT_REPUBLISH     [8] light iterations between republishes of the
- *                        running maximum register, a power of two.
+ *                        running maximum register at k <= 256, a power of
+ *                        two; scaled by k/256 above (a republish reads all
+ *                        k registers).  The segment path republishes every
+ *                        max(4, k/64) batches, rounded up to a power of two.
  *   GM_OPT_SEG_REST      [12] an element whose expected number of further
  *                        arrivals below the threshold (k v_i (T - t_1))
  *                        exceeds this goes to the segment path straight

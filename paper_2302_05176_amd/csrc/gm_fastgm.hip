@@ -279,6 +279,14 @@ __device__ __forceinline__ void reg_update(const VecCtx& c, int32_t srv, double 
   if (c.mode == kWalkNormal) contest_check(c, old, pk);
 }
 
+// Power of two at least max(4, k / 64): the segment path's batches between
+// threshold republishes.
+__device__ __forceinline__ int republish_period(int k) {
+  int p = 4;
+  while (p * kWave < k) p <<= 1;
+  return p;
+}
+
 // max_j y_j as seen now (+inf while a register is empty).  The keys are
 // non-negative doubles or +inf, whose order is that of their bit patterns:
 // each lane takes a double maximum (one instruction per register), the wave
@@ -571,6 +579,11 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, const lds_i
   int z0 = 1;
   int batches = 0, elems = 0;  // per segment (statistics only)
   int round = 0;               // wave-uniform batch counter
+  // Batches between threshold republishes: a republish reads all k
+  // registers (k/64 per lane), so it is spread over about k/64 batches, at
+  // least 4 (document batch at k = 4096: every 4 batches 15.5 ms, every 64
+  // 12.6 ms; at k = 1024: every 4 2.13 ms, every 16 2.06 ms).
+  const int rp_mask = republish_period(k) - 1;
   // contest check deferred by one batch (hides the atomic's latency)
   bool pend = false;
   unsigned long long pend_old = 0, pend_pk = 0;
@@ -689,7 +702,7 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, const lds_i
         z0 += G;
     }
     // the republish is a wave-wide reduction: keep its condition wave-uniform
-    if (c.mode == kWalkNormal && (++round & 3) == 0) T = fmin(T, wave_max_register(c));
+    if (c.mode == kWalkNormal && (++round & rp_mask) == 0) T = fmin(T, wave_max_register(c));
   }
   if (pend) contest_check(c, pend_old, pend_pk);
   if (c.stats) {
@@ -961,7 +974,9 @@ __device__ int walk_wave(const VecCtx& c, lds_i32* cursor, double& T, HeavyRec* 
         }
       }
       ++iter;
-      if (c.mode == kWalkNormal && (iter & (c.republish - 1)) == 0)
+      // (the option's period at k <= 256, scaled with k above: each
+      // republish reads k/64 registers per lane)
+      if (c.mode == kWalkNormal && (iter & (c.republish * (republish_period(c.k) / 4) - 1)) == 0)
         T = fmin(T, wave_max_register(c));
     }
     const uint64_t om = __ballot(overflow);
