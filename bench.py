@@ -203,18 +203,20 @@ def summarize_pmc(args):
         rec = {}
     rec[workload] = {n: e for n, e in out.items() if "elementwise" not in n and "__amd" not in n}
     wl = "" if args.workload == "batch" else f" --workload {args.workload}"
-    extra = (" --steps 3 --warmup 1 --no-cpu-baseline --no-extras" if args.workload == "batch"
-             else " --steps 2 --warmup 1 --no-autotune")
+    extra = {"batch": " --steps 3 --warmup 1 --no-cpu-baseline --no-extras",
+             "stream": " --steps 2 --warmup 1",
+             "uneven": " --steps 2 --warmup 1 --no-autotune"}.get(args.workload, " --steps 2 --warmup 1")
+    kk = f" --k {args.k}" if args.workload == "batch" else ""
+    fdir, wdir = (os.path.relpath(os.path.abspath(d), ROOT) for d in args.summarize_pmc)
     rec.setdefault("_commands", {})
     if isinstance(rec["_commands"], list):
         rec["_commands"] = {}
     rec["_commands"][workload] = [
-        f"cd /tmp && timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc_{workload}_FETCH_SIZE -o run -- "
-        f"python3 <repo>/bench.py{wl}{extra} --copy-bytes 1073741824",
-        f"cd /tmp && timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <repo>/gpurun_out/pmc_{workload}_WRITE_SIZE -o run -- "
-        f"python3 <repo>/bench.py{wl}{extra} --copy-bytes 1073741824",
-        f"python bench.py{wl} --summarize-pmc gpurun_out/pmc_{workload}_FETCH_SIZE gpurun_out/pmc_{workload}_WRITE_SIZE "
-        f"--copy-bytes 1073741824 --k {args.k}",
+        f"cd /tmp && timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/{fdir} -o run -- "
+        f"python3 <repo>/bench.py{wl}{kk if args.k != 256 else ''}{extra} --copy-bytes 1073741824",
+        f"cd /tmp && timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <repo>/{wdir} -o run -- "
+        f"python3 <repo>/bench.py{wl}{kk if args.k != 256 else ''}{extra} --copy-bytes 1073741824",
+        f"python bench.py{wl} --summarize-pmc {fdir} {wdir} --copy-bytes 1073741824{kk}",
         "FETCH_SIZE and WRITE_SIZE are KiB per dispatch; each is scaled by copy_bytes / (what it reads for the "
         "calibration elementwise kernel that reads and writes copy_bytes)"]
     with open(TRAFFIC_FILE, "w") as f:
