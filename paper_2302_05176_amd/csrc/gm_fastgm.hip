@@ -318,9 +318,10 @@ __device__ __forceinline__ double recip_step(int m) { return kRecip.v[m]; }
 // Segment path.  An element whose displaced-position table fills up is walked
 // on by a segment of G lanes (G = 8: half a DPP row, eight elements per
 // wave; G = 16: one row, four elements; G = 64: the whole wave), G
-// consecutive arrivals per batch.  Its permutation is dense in LDS (one u16 per position, tagged with a
-// 3-bit generation so that a stale entry reads as the identity and a new
-// element needs no initialisation).
+// consecutive arrivals per batch.  Its permutation is dense in LDS: one u16
+// per position, the value minus one in 12 bits (k <= 4096) under a 4-bit
+// generation, so that a stale entry reads as the identity and only every
+// 15th element of a segment clears the area.
 
 // Bit 0 of every G-lane segment of the wave.
 template <int G>
@@ -626,16 +627,20 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, const lds_i
         active = true;
         have_rec = false;
         ++elems;
-        hgen = hgen == 7u ? 1u : hgen + 1u;
-        if (hgen == 1u)
-          for (int q = li; q <= k; q += G) pm[q] = 0;
+        hgen = hgen == 15u ? 1u : hgen + 1u;
+        if (hgen == 1u) {
+          // every 15th element: clear positions 0..k, four per 8-byte store
+          // (the segment's area starts on an 8-byte boundary)
+          lds_u64* p8 = reinterpret_cast<lds_u64*>(pm);
+          for (int q = li; q < (k + 4) / 4; q += G) p8[q] = 0ull;
+        }
         // the displaced positions of the walk so far (dwords 16 + e)
 #pragma unroll
         for (int cc = 0; cc < D; ++cc) {
           const int e = li * D + cc - 16;
           if (e >= 0 && e < nent) {
             const uint32_t en = rec[cc];
-            pm[(en >> 12) + 1] = static_cast<uint16_t>((hgen << 13) | ((en & 0xFFFu) + 1));
+            pm[(en >> 12) + 1] = static_cast<uint16_t>((hgen << 12) | (en & 0xFFFu));
           }
         }
       }
@@ -679,14 +684,14 @@ __device__ void segment_walk(const VecCtx& c, const HeavyRec* heavy, const lds_i
     const int f = rs ? __ffsll(static_cast<long long>(rs)) - 1 : nval;
     uint32_t cval = 0, disp = 0;
     if (li < f) {
-      cval = (ej >> 13) == hgen ? (ej & 0x1FFFu) : static_cast<uint32_t>(j);
-      disp = (ez >> 13) == hgen ? (ez & 0x1FFFu) : static_cast<uint32_t>(z);
+      cval = (ej >> 12) == hgen ? (ej & 0xFFFu) + 1u : static_cast<uint32_t>(j);
+      disp = (ez >> 12) == hgen ? (ez & 0xFFFu) + 1u : static_cast<uint32_t>(z);
     }
     const int32_t jf = li < f ? j : -1 - li;
     const bool inwin = __ballot(li < f && j > z && j < z0 + f) != 0;
     const bool killed =
         fy_batch<G>(std::make_integer_sequence<int, G>{}, jf, z, inwin, cval, disp);
-    if (li < f && !killed) pm[j] = static_cast<uint16_t>((hgen << 13) | disp);
+    if (li < f && !killed) pm[j] = static_cast<uint16_t>((hgen << 12) | (disp - 1u));
     if (li < f) {
       pend_pk = packed_key(c, t, ind);
       pend_old = reg_offer(c, static_cast<int32_t>(cval) - 1, t, pend_pk, ind);
