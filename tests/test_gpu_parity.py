@@ -238,6 +238,19 @@ def test_batched_plain_small(gm):
                      (ws, wy), f"v={v}")
 
 
+@pytest.mark.parametrize("k", [2, 3, 17, 1024, 1025, 4099, 9001])
+def test_wcard_widths(gm, k):
+    """The weighted-cardinality sum is staged through LDS 1024 registers at
+    a time and added 16 per step with a tail: widths around both edges, with
+    values spread over many binades so that the order of the additions shows,
+    must give the oracle's left-to-right sum bit for bit."""
+    rng = np.random.default_rng(k)
+    y = np.exp(rng.uniform(-30.0, 5.0, size=(5, k)))
+    C = gm.wcard_est(torch.from_numpy(y).to(DEV)).cpu().numpy()
+    Co = np.array([oracle.wcard(y[r]) for r in range(len(y))])
+    assert np.array_equal(C.view(np.uint64), Co.view(np.uint64)), f"k={k}"
+
+
 def test_estimators_match_oracle(gm):
     idx, w, off, frac = W.pairs(npairs=200, seed=31)
     k = 256
