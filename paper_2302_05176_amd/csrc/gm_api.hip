@@ -88,7 +88,7 @@ constexpr int64_t kNoAllocRegs = 1ll << 19;
 constexpr int64_t kNoAllocCounters = 4096;
 constexpr size_t kNoAllocScratchBytes =
     static_cast<size_t>(kNoAllocRegs) * (sizeof(double) + sizeof(int32_t)) +
-    2 * sizeof(int32_t) * static_cast<size_t>(kNoAllocCounters);
+    2 * sizeof(int32_t) * static_cast<size_t>(kNoAllocCounters) + gm::kPlainPlanBytes;
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 struct DeviceState {
@@ -209,7 +209,8 @@ gm_status plan_workspace(DeviceState* st, hipStream_t stream, int64_t nvec, Plan
 
 size_t plain_scratch_bytes(int cus) {
   return static_cast<size_t>(gm::plain_scratch_regs(cus)) * (sizeof(double) + sizeof(int32_t)) +
-         2 * sizeof(int32_t) * static_cast<size_t>(gm::plain_scratch_counters(cus));
+         2 * sizeof(int32_t) * static_cast<size_t>(gm::plain_scratch_counters(cus)) +
+         gm::kPlainPlanBytes;
 }
 
 // Scratch of split plain launches on `stream` (created on first use, with

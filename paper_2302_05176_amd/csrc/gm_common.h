@@ -101,6 +101,12 @@ __device__ __forceinline__ int wave_sum_i32(int v) {
   return v;
 }
 
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
 __device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
@@ -125,7 +131,12 @@ struct SketchArgs {
 
 // Scratch handed to a plain-form launch for splitting vectors over
 // workgroups (see launch_plain): `regs` partial registers (8-byte values,
-// then 4-byte indices) followed by two arrays of `counters` int32.
+// then 4-byte indices) followed by two arrays of `counters` int32 and
+// kPlainPlanBytes of split plan.
+// Bytes after the counters that hold a split plan for batches of uneven
+// vectors (gm_plain.hip).
+constexpr size_t kPlainPlanBytes = 32768;
+
 struct PlainScratch {
   void* base;         // nullptr: the launch does not split
   int64_t regs;

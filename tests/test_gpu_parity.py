@@ -597,6 +597,24 @@ def test_plain_split_few_vectors(gm, k):
                  oracle.sketch(bi, bw, bo, k, 4, form=oracle.FORM_PLAIN), f"batch k={k}")
 
 
+@pytest.mark.parametrize("k", [256, 1024])
+def test_plain_uneven_batch_split(gm, k):
+    """A batch of many vectors (more (vector, tile) pairs than half the
+    target workgroups) goes through the planning pass: the few vectors far
+    above the mean work per workgroup are split and merged, the rest are
+    not; every register against the oracle, over two calls (the merge
+    counters are reused)."""
+    rng = np.random.default_rng(1031 + k)
+    sizes = rng.integers(50, 600, size=1100)
+    sizes[[10, 500, 1000, 1099]] = [60_000, 120_000, 20_000, 9_000]
+    bi, bw, bo = W.batch(nvec=len(sizes), seed=1032, sizes=sizes)
+    oracle.set_threads(16)
+    want = oracle.sketch(bi, bw, bo, k, 6, form=oracle.FORM_PLAIN)
+    for rep in range(2):
+        print(f"plain uneven batch k={k} call {rep}", flush=True)
+        _assert_same(_gpu_sketch(gm, bi, bw, bo, k, 6, "plain"), want, f"k={k} call {rep}")
+
+
 def test_plain_split_poison_and_batched(gm):
     """Split launches: an invalid entry in one range of a long vector poisons
     the whole vector (once in the error counter), and per-vector k in a
