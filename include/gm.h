@@ -134,8 +134,9 @@ gm_status gm_sketch_plain(const int32_t *indices, const float *weights, const in
  * error rules as gm_sketch_plain; it calls no hipMalloc, hipFree or other
  * allocating routine, not even on its first call on a device.
  *   Scratch: the partial registers of a split launch live in one static
- *   device array per device of 6 MiB + 32 KiB (2^19 partial registers and
- *   2 x 4096 int32 counters), held until the process ends.  A call splits
+ *   device array per device of 6 MiB + 64 KiB (2^19 partial registers,
+ *   2 x 4096 int32 counters and a 32 KiB split plan for batches of many
+ *   vectors), held until the process ends.  A call splits
  *   its vectors only as far as that array holds (one vector at any k fits
  *   the full split); a call that would need more runs with fewer entry
  *   ranges, so no input is rejected for its size.  The counters are cleared
