@@ -472,6 +472,8 @@ def stream_kernel_rooflines(breakdown, n, k):
             ent[name] = kernel_roofline(name, ms, k * harmonic(k), ARRIVAL_SLOTS,
                                         "arrivals (k H_k beyond the first arrivals)",
                                         hbm_bytes=12.0 * k, bound="alu", traffic=tr)
+            ent[name]["note"] = ("one vector's candidate walk: a few workgroups, each a chain of "
+                                 "dependent batches, so its time is latency, far below the VALU line")
     return ent
 
 
