@@ -1724,9 +1724,19 @@ __global__ __launch_bounds__(kBigBlock) void big_sum_kernel(FastArgs fa) {
   const int32_t* list2 = fa.list + fa.plan->offset[kBigFirst];
   const int64_t total = fa.plan->big_chunks;
   const int tid = threadIdx.x;
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const int b = big_of_chunk(fa.big, c2, t);
-    const VecDesc d = vec_desc(p, list2[b]);
+  // a contiguous run of chunks per workgroup: the owning vector is looked
+  // up when the run enters it, not for every chunk
+  const int64_t t0 = total * blockIdx.x / gridDim.x;
+  const int64_t t1 = total * (blockIdx.x + 1) / gridDim.x;
+  int b = -1;
+  int64_t next_vec_chunk = -1;
+  VecDesc d{};
+  for (int64_t t = t0; t < t1; ++t) {
+    if (t >= next_vec_chunk) {
+      b = big_of_chunk(fa.big, c2, t);
+      d = vec_desc(p, list2[b]);
+      next_vec_chunk = b + 1 < c2 ? fa.big[b + 1].chunk_base : total;
+    }
     if (d.bad) continue;
     const int64_t e0 = d.a + (t - fa.big[b].chunk_base) * kBigChunk;
     const int64_t e1 = e0 + kBigChunk < d.b ? e0 + kBigChunk : d.b;
@@ -2213,7 +2223,7 @@ hipError_t launch_fastgm(const SketchArgs& s, int pos_bits, double t0_scale, int
   hipLaunchKernelGGL(big_probe_kernel, dim3(cus * probe_wg), dim3(kBigBlock), 0, stream, fa);
   timing_end(tid, ta, stream);
   tid = timing_begin("big_gather_kernel", false, stream, &ta);
-  hipLaunchKernelGGL(big_gather_kernel, dim3(cus * 2), dim3(kBigBlock), 0, stream, fa);
+  hipLaunchKernelGGL(big_gather_kernel, dim3(cus * 8), dim3(kBigBlock), 0, stream, fa);
   timing_end(tid, ta, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
