@@ -134,8 +134,10 @@ constexpr int64_t kBigChunk = 8192;
 // register of the merged sketch, and walks up to T0 at most; so if no merged
 // register is empty, the merge is the sketch of the vector.  Otherwise the
 // last part walks the vector alone, as an unsplit vector is walked.
+// (Stream vector, 10^7 entries, k = 1024, about 15,000 candidates: parts of
+// 2048, 1536 and 1024 candidates gave 0.111, 0.109 and 0.115 ms per sketch.)
 constexpr int kMaxParts = 16;
-constexpr int kPartCand = 2048;
+constexpr int kPartCand = 1536;
 constexpr int kSplitMaxBig = 16;
 constexpr int64_t kPartRegs = static_cast<int64_t>(kSplitMaxBig) * kMaxParts * GM_K_MAX;
 
